@@ -1,0 +1,201 @@
+/*
+ * mbl.h -- C ABI of the MI355X matrix-free interior eigensolver for the
+ * random-field spin-1/2 chain (Van Beeumen, Ibrahim, Kahanamoku-Meyer, Yao,
+ * Yang, "Enhancing Scalability of a Matrix-Free Eigensolver for Studying
+ * Many-Body Localization", arXiv 2012.00217).
+ *
+ * Model (paper eq. (1)/(2), Sec. 2.1), open chain of L sites, S = sigma/2:
+ *   H = J sum_{i=0}^{L-2} [S^x_i S^x_{i+1} + S^y_i S^y_{i+1} + Delta S^z_i S^z_{i+1}]
+ *       + sum_{i=0}^{L-1} h_i S^z_i
+ * J = Delta = 1 is eq. (1).  H conserves total S^z; every call works in one
+ * sector, nup = Sz + L/2 up spins, dimension n = C(L, nup) (Table 1).
+ *
+ * Basis convention: site i is bit i of an integer state; bit 1 = spin up.
+ * Row r of every block is the r-th state of the sector in ascending integer
+ * order.  Blocks are row-major n x b with an explicit leading dimension
+ * (in elements); FP64 blocks are double, FP32 blocks are float.
+ *
+ * Ownership: h is copied at create time; the handle owns its device tables.
+ * Block arguments (X, Y, R, W, evecs, Gram outputs) are device pointers owned
+ * by the caller.  Host pointers are marked _host.  Work buffers are device
+ * memory the library allocates (hipMalloc, or the callback installed with
+ * mbl_set_allocator) and frees before the call returns, except the per-handle
+ * tables, freed by mbl_hamiltonian_destroy.
+ *
+ * Errors: every call returns an mbl_status (MBL_OK == 0, errors < 0).  No C++
+ * exception and no abort crosses this boundary.  mbl_last_error() returns a
+ * thread-local message for the last failure on the calling thread.
+ * Arguments are validated before any device work is enqueued; a call that
+ * returns MBL_EINVAL has not touched device memory.
+ *
+ * Streams: calls marked "async" only enqueue work on the given stream and
+ * return; the others synchronise that stream before returning.  Handles are
+ * thread-compatible, not thread-safe: do not use one handle from two threads
+ * at once.
+ */
+#ifndef MBL_H_
+#define MBL_H_
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MBL_OK = 0,
+  MBL_EINVAL = -1,      /* invalid argument (nothing was enqueued)           */
+  MBL_ENOMEM = -2,      /* device allocation failed                           */
+  MBL_EDEVICE = -3,     /* a HIP runtime call failed                          */
+  MBL_ENOCONV = -4,     /* solver hit its iteration limit; best pairs returned */
+  MBL_EBREAKDOWN = -5,  /* basis collapsed (e.g. starting block rank-deficient) */
+  MBL_EINTERNAL = -8    /* unexpected internal failure                        */
+} mbl_status;
+
+typedef enum {
+  MBL_F64 = 0,    /* everything in FP64                                       */
+  MBL_F32 = 1,    /* FP32 blocks (apply / PCG kernels only; not a solve mode) */
+  MBL_MIXED = 2,  /* solve: FP32 apply, block updates, FP32-MFMA Gram and FP32
+                     PCG; FP64 small dense algebra; then a closing FP64 pass
+                     (FP64 blocks, FP32 PCG) down to the tolerance           */
+  MBL_PCG32 = 3   /* solve: FP64 blocks and Rayleigh-Ritz, FP32 PCG only
+                     (the precision split of the paper, Sec. 6)               */
+} mbl_precision;
+
+typedef struct mbl_ham_s* mbl_ham;
+
+/* Allocation callbacks (optional).  alloc returns device memory of at least
+ * `bytes` usable on `stream`, or NULL; free releases it.  NULL, NULL restores
+ * hipMalloc/hipFree.  Not thread-safe with concurrent library calls. */
+typedef void* (*mbl_alloc_fn)(size_t bytes, hipStream_t stream, void* ctx);
+typedef void (*mbl_free_fn)(void* ptr, hipStream_t stream, void* ctx);
+mbl_status mbl_set_allocator(mbl_alloc_fn alloc, mbl_free_fn free_fn, void* ctx);
+
+const char* mbl_last_error(void);
+int mbl_version(void);
+
+/* ---- sector and Hamiltonian (paper Sec. 2.1, eq. (1)/(2)) ---------------- */
+
+/* Build the handle for one sector: validates 2 <= L <= 32, 2*Sz integer with
+ * the parity of L and |Sz| <= L/2, finite J, Delta, h_host[0..L-1].  Builds
+ * the Pascal table C(i, t), the state list (uint32 per row) and the diagonal
+ * <s|H|s> on the device (async on `stream`, which is synchronised before
+ * return).  The sector's sparsity pattern is independent of h (Sec. 4.2), so
+ * the tables could be shared between realisations; here each handle owns its
+ * own. */
+mbl_status mbl_hamiltonian_create(int L, double Sz, double J, double Delta,
+                                  const double* h_host, hipStream_t stream,
+                                  mbl_ham* out);
+mbl_status mbl_hamiltonian_destroy(mbl_ham H);
+mbl_status mbl_hamiltonian_dim(mbl_ham H, int64_t* n);
+
+/* The n sector states in row order, as 64-bit integers (host output). */
+mbl_status mbl_sector_states(mbl_ham H, uint64_t* states_host);
+
+/* Row index of each query state (host arrays); -1 if the state is not in the
+ * sector (wrong number of up spins or a bit at position >= L). */
+mbl_status mbl_rank(mbl_ham H, const uint64_t* states_host, int64_t count,
+                    int64_t* idx_host);
+
+/* diag_dev[r] = <s_r|H|s_r>; jacobi_dev[r] = diag of (H - sigma I)^2 for row
+ * r, the Jacobi preconditioner of the PCG inner solve (Sec. 3.2).  Either
+ * output may be NULL.  Device FP64 arrays of length n.  Async. */
+mbl_status mbl_diagonal(mbl_ham H, double sigma, double* diag_dev,
+                        double* jacobi_dev, hipStream_t stream);
+
+/* ---- matrix-free block apply (paper Sec. 3.2 and 4.1) -------------------- */
+
+/* Y = (H - sigma I) X for an n x b block, never forming H.  prec MBL_F64 or
+ * MBL_F32 selects the element type of X and Y.  ldx, ldy >= b.  X and Y must
+ * not overlap.  Async. */
+mbl_status mbl_apply_block(mbl_ham H, double sigma, mbl_precision prec,
+                           const void* X, int64_t ldx, void* Y, int64_t ldy,
+                           int b, hipStream_t stream);
+
+/* Y = (H - sigma I)^2 X, the spectral fold (Sec. 3.2), as two applies through
+ * the caller's intermediate T = (H - sigma I) X (n x b, ldt >= b).  Async. */
+mbl_status mbl_fold_apply(mbl_ham H, double sigma, mbl_precision prec,
+                          const void* X, int64_t ldx, void* T, int64_t ldt,
+                          void* Y, int64_t ldy, int b, hipStream_t stream);
+
+/* W = m steps of Jacobi-preconditioned CG on (H - sigma I)^2 W = R, each
+ * column independently, starting from W = 0 (the LOBPCG preconditioner,
+ * Sec. 3.2).  prec MBL_F64 or MBL_F32 is the element type of R, W and of the
+ * CG arithmetic.  m >= 0.  Synchronises `stream`. */
+mbl_status mbl_pcg(mbl_ham H, double sigma, mbl_precision prec, const void* R,
+                   int64_t ldr, void* W, int64_t ldw, int b, int m,
+                   hipStream_t stream);
+
+/* ---- dense block kernels (LOBPCG's matrix-matrix work, Sec. 3.2 (ii)) ---- */
+
+/* C_dev (p x q, row-major, ldc >= q, FP64) = A^T B for n x p A and n x q B of
+ * element type prec (MBL_F64 or MBL_F32), reduced in a fixed order (results
+ * are bitwise reproducible).  Matrix-core (MFMA) kernel.  Async. */
+mbl_status mbl_gram(mbl_precision prec, int64_t n, const void* A, int64_t lda,
+                    int p, const void* B, int64_t ldb, int q, double* C_dev,
+                    int64_t ldc, hipStream_t stream);
+
+/* Y (n x q) = A (n x p) C (p x q, FP64 device, row-major ldc) in element type
+ * prec.  Y must not overlap A.  Async. */
+mbl_status mbl_block_combine(mbl_precision prec, int64_t n, const void* A,
+                             int64_t lda, int p, const double* C_dev,
+                             int64_t ldc, void* Y, int64_t ldy, int q,
+                             hipStream_t stream);
+
+/* Symmetric eigendecomposition of an m x m FP64 device matrix (row-major,
+ * lda >= m; only read): w_dev ascending, V_dev columns the eigenvectors
+ * (row-major, ldv >= m).  One-workgroup cyclic Jacobi.  m <= 1024.  Async. */
+mbl_status mbl_small_eigh(int m, const double* A_dev, int64_t lda,
+                          double* w_dev, double* V_dev, int64_t ldv,
+                          hipStream_t stream);
+
+/* ---- eigensolver (paper Sec. 3.2) ---------------------------------------- */
+
+/* Extreme eigenvalues of H in the sector, each to absolute accuracy `tol`
+ * (tol >= 1e-14), by LOBPCG on H and on -H.  Synchronises `stream`. */
+mbl_status mbl_spectrum_bounds(mbl_ham H, double tol, double* emin,
+                               double* emax, hipStream_t stream);
+
+typedef struct {
+  int max_iter;          /* LOBPCG outer iterations (default 400)            */
+  int pcg_iters;         /* CG steps per LOBPCG iteration; 0 = by dimension  */
+  int precision;         /* mbl_precision: MBL_F64, MBL_MIXED or MBL_PCG32   */
+  int verbose;           /* 1: one line per outer iteration on stderr        */
+  uint64_t seed;         /* starting block (device counter-based generator)  */
+} mbl_solve_opts;
+
+typedef struct {
+  int iters;             /* outer LOBPCG iterations in total                 */
+  int iters_fp64;        /* of which in the closing FP64 pass (MBL_MIXED)    */
+  int nconv;             /* wanted pairs with residual <= tol                */
+  int64_t applies;       /* block applies of (H - sigma I), all kernels      */
+  int64_t pcg_steps;     /* CG steps in total                                */
+  double seconds;        /* wall time of the call                            */
+  double t_pcg;          /* seconds in the PCG inner solves                  */
+  double t_rr;           /* seconds in Gram / Rayleigh-Ritz / orthonormalising */
+  double max_resid;      /* max ||H x - lambda x||_2 over the returned pairs */
+} mbl_solve_info;
+
+mbl_status mbl_solve_opts_default(mbl_solve_opts* opts);
+
+/* The nev eigenpairs of H with eigenvalues nearest sigma, by LOBPCG with
+ * block size `block` on the spectral fold (H - sigma I)^2, preconditioned by
+ * Jacobi-PCG (Sec. 3.2).  Converged when every wanted pair has
+ * ||H x - lambda x||_2 <= tol (absolute, unit x, evaluated in FP64 with a
+ * fresh apply).  Requires 1 <= nev <= block, 2 * block <= n, tol > 0.
+ * Outputs: evals_host[nev] ascending, resid_host[nev], evecs_dev (n x nev
+ * FP64 row-major, ldv >= nev; may be NULL), info (may be NULL); opts NULL =
+ * defaults.  Returns MBL_ENOCONV with the best pairs if max_iter is reached.
+ * Synchronises `stream`. */
+mbl_status mbl_lobpcg_solve(mbl_ham H, double sigma, int nev, int block,
+                            double tol, const mbl_solve_opts* opts,
+                            double* evals_host, double* evecs_dev, int64_t ldv,
+                            double* resid_host, mbl_solve_info* info,
+                            hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MBL_H_ */

@@ -1,0 +1,197 @@
+"""Python binding of libmbl: argument marshalling only.
+
+Every numerical step runs in the HIP kernels of libmbl.so; this module turns
+torch tensors into device pointers and streams and checks status codes.
+Blocks are row-major (n, b) tensors on a HIP device; FP64 or FP32.
+"""
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import MBL_F32, MBL_F64, MBL_MIXED, MBL_PCG32, MblError  # noqa: F401
+
+PRECISIONS = {"f64": MBL_F64, "mixed": MBL_MIXED, "pcg32": MBL_PCG32}
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _prec(t):
+    if t.dtype == torch.float64:
+        return MBL_F64
+    if t.dtype == torch.float32:
+        return MBL_F32
+    raise TypeError(f"blocks must be float64 or float32, got {t.dtype}")
+
+
+def _block(t, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError(f"{name} must be a row-major 2-D tensor (unit column stride)")
+    return C.c_void_p(t.data_ptr()), t.stride(0)
+
+
+class Hamiltonian:
+    """One S^z sector of the random-field spin chain (paper eq. (1)/(2))."""
+
+    def __init__(self, L, h, Sz=0.0, J=1.0, Delta=1.0, stream=None):
+        lib = _lib.load()
+        h = np.ascontiguousarray(np.asarray(h, dtype=np.float64))
+        if h.shape != (L,):
+            raise ValueError("h must have length L")
+        self.L, self.Sz, self.J, self.Delta = int(L), float(Sz), float(J), float(Delta)
+        self.h = h.copy()
+        handle = C.c_void_p()
+        _lib.check(lib.mbl_hamiltonian_create(
+            self.L, self.Sz, self.J, self.Delta, h.ctypes.data_as(_lib.dptr), _stream(stream),
+            C.byref(handle)))
+        self._h = handle
+        n = C.c_int64()
+        _lib.check(lib.mbl_hamiltonian_dim(self._h, C.byref(n)))
+        self.n = n.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.load().mbl_hamiltonian_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- sector --------------------------------------------------------------
+    def states(self):
+        out = np.empty(self.n, dtype=np.uint64)
+        _lib.check(_lib.load().mbl_sector_states(self._h, out.ctypes.data_as(_lib.u64p)))
+        return out
+
+    def rank(self, states):
+        q = np.ascontiguousarray(np.asarray(states, dtype=np.uint64))
+        out = np.empty(q.shape, dtype=np.int64)
+        _lib.check(_lib.load().mbl_rank(self._h, q.ctypes.data_as(_lib.u64p), q.size,
+                                        out.ctypes.data_as(_lib.i64p)))
+        return out
+
+    def diagonal(self, sigma=0.0, device="cuda", stream=None):
+        d = torch.empty(self.n, dtype=torch.float64, device=device)
+        j = torch.empty(self.n, dtype=torch.float64, device=device)
+        _lib.check(_lib.load().mbl_diagonal(self._h, float(sigma), C.c_void_p(d.data_ptr()),
+                                            C.c_void_p(j.data_ptr()), _stream(stream)))
+        return d, j
+
+    # -- operators -----------------------------------------------------------
+    def apply(self, X, sigma=0.0, out=None, stream=None):
+        """(H - sigma I) X."""
+        px, ldx = _block(X, "X")
+        Y = torch.empty_like(X, memory_format=torch.contiguous_format) if out is None else out
+        py, ldy = _block(Y, "Y")
+        _lib.check(_lib.load().mbl_apply_block(self._h, float(sigma), _prec(X), px, ldx, py, ldy,
+                                               X.shape[1], _stream(stream)))
+        return Y
+
+    def fold_apply(self, X, sigma=0.0, stream=None):
+        """(H - sigma I)^2 X (returns Y, and the intermediate (H - sigma I) X)."""
+        px, ldx = _block(X, "X")
+        T = torch.empty_like(X, memory_format=torch.contiguous_format)
+        Y = torch.empty_like(X, memory_format=torch.contiguous_format)
+        pt, ldt = _block(T, "T")
+        py, ldy = _block(Y, "Y")
+        _lib.check(_lib.load().mbl_fold_apply(self._h, float(sigma), _prec(X), px, ldx, pt, ldt,
+                                              py, ldy, X.shape[1], _stream(stream)))
+        return Y, T
+
+    def pcg(self, R, sigma, m, stream=None):
+        """m Jacobi-PCG steps on (H - sigma)^2 W = R, per column, from W = 0."""
+        pr, ldr = _block(R, "R")
+        W = torch.empty_like(R, memory_format=torch.contiguous_format)
+        pw, ldw = _block(W, "W")
+        _lib.check(_lib.load().mbl_pcg(self._h, float(sigma), _prec(R), pr, ldr, pw, ldw,
+                                       R.shape[1], int(m), _stream(stream)))
+        return W
+
+    def spectrum_bounds(self, tol=1e-12, stream=None):
+        lo, hi = C.c_double(), C.c_double()
+        _lib.check(_lib.load().mbl_spectrum_bounds(self._h, float(tol), C.byref(lo), C.byref(hi),
+                                                   _stream(stream)))
+        return lo.value, hi.value
+
+    def solve(self, sigma, nev, block, tol=1e-10, precision="f64", max_iter=400, pcg_iters=0,
+              seed=0x5EED, verbose=False, want_vectors=True, device="cuda", stream=None,
+              raise_on_noconv=True):
+        """nev eigenpairs nearest sigma by LOBPCG on the spectral fold.
+
+        Returns (evals [nev] numpy, evecs (n, nev) float64 tensor or None,
+        resid [nev] numpy, info dict).
+        """
+        lib = _lib.load()
+        opts = _lib.SolveOpts()
+        _lib.check(lib.mbl_solve_opts_default(C.byref(opts)))
+        opts.max_iter = int(max_iter)
+        opts.pcg_iters = int(pcg_iters)
+        opts.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        opts.verbose = int(bool(verbose))
+        opts.seed = int(seed)
+        ev = np.zeros(nev)
+        rs = np.zeros(nev)
+        info = _lib.SolveInfo()
+        V = torch.empty((self.n, nev), dtype=torch.float64, device=device) if want_vectors else None
+        st = lib.mbl_lobpcg_solve(
+            self._h, float(sigma), int(nev), int(block), float(tol), C.byref(opts),
+            ev.ctypes.data_as(_lib.dptr), C.c_void_p(V.data_ptr()) if V is not None else None,
+            nev, rs.ctypes.data_as(_lib.dptr), C.byref(info), _stream(stream))
+        _lib.check(st, allow=() if raise_on_noconv else (_lib.MBL_ENOCONV,))
+        d = {f: getattr(info, f) for f, _ in _lib.SolveInfo._fields_}
+        d["status"] = _lib.STATUS_NAMES.get(st, st)
+        return ev, V, rs, d
+
+
+def gram(A, B, stream=None):
+    """A^T B in FP64 (matrix-core kernel, fixed-order reduction)."""
+    pa, lda = _block(A, "A")
+    pb, ldb = _block(B, "B")
+    if A.dtype != B.dtype or A.shape[0] != B.shape[0]:
+        raise ValueError("A and B must share dtype and row count")
+    Cm = torch.empty((A.shape[1], B.shape[1]), dtype=torch.float64, device=A.device)
+    _lib.check(_lib.load().mbl_gram(_prec(A), A.shape[0], pa, lda, A.shape[1], pb, ldb,
+                                    B.shape[1], C.c_void_p(Cm.data_ptr()), B.shape[1],
+                                    _stream(stream)))
+    return Cm
+
+
+def block_combine(A, Cm, stream=None):
+    """A @ Cm with Cm an FP64 (p, q) device matrix; result in A's dtype."""
+    pa, lda = _block(A, "A")
+    Cm = Cm.contiguous()
+    if Cm.dtype != torch.float64 or Cm.shape[0] != A.shape[1]:
+        raise ValueError("C must be float64 with p rows")
+    Y = torch.empty((A.shape[0], Cm.shape[1]), dtype=A.dtype, device=A.device)
+    py, ldy = _block(Y, "Y")
+    _lib.check(_lib.load().mbl_block_combine(_prec(A), A.shape[0], pa, lda, A.shape[1],
+                                             C.c_void_p(Cm.data_ptr()), Cm.shape[1], py, ldy,
+                                             Cm.shape[1], _stream(stream)))
+    return Y
+
+
+def small_eigh(A, stream=None):
+    """Symmetric eigendecomposition of a small FP64 device matrix (Jacobi)."""
+    A = A.contiguous()
+    m = A.shape[0]
+    w = torch.empty(m, dtype=torch.float64, device=A.device)
+    V = torch.empty((m, m), dtype=torch.float64, device=A.device)
+    _lib.check(_lib.load().mbl_small_eigh(m, C.c_void_p(A.data_ptr()), m, C.c_void_p(w.data_ptr()),
+                                          C.c_void_p(V.data_ptr()), m, _stream(stream)))
+    return w, V

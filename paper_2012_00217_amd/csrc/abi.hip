@@ -1,0 +1,338 @@
+// extern "C" boundary of libmbl: argument validation, status codes,
+// thread-local error messages and the allocator hook.  Every entry point
+// catches everything: no exception crosses the C ABI.
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "common.h"
+
+namespace mbl {
+namespace {
+
+thread_local std::string g_last_error;
+mbl_alloc_fn g_alloc = nullptr;
+mbl_free_fn g_free = nullptr;
+void* g_ctx = nullptr;
+
+template <class F>
+mbl_status guard(F&& f) {
+  try {
+    return f();
+  } catch (const Error& e) {
+    g_last_error = e.what();
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return MBL_ENOMEM;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return MBL_EINTERNAL;
+  } catch (...) {
+    g_last_error = "unknown failure";
+    return MBL_EINTERNAL;
+  }
+}
+
+void require(bool ok, const char* what) {
+  if (!ok) fail(MBL_EINVAL, what);
+}
+
+const Ham& ham(mbl_ham h) {
+  require(h != nullptr, "null Hamiltonian handle");
+  return *reinterpret_cast<const Ham*>(h);
+}
+
+bool block_prec(int p) { return p == MBL_F64 || p == MBL_F32; }
+
+}  // namespace
+
+void* dev_alloc(size_t bytes, hipStream_t s) {
+  void* p = nullptr;
+  if (g_alloc) {
+    p = g_alloc(bytes, s, g_ctx);
+    if (!p) fail(MBL_ENOMEM, "allocator callback returned NULL for " + std::to_string(bytes) + " bytes");
+    return p;
+  }
+  MBL_HIP(hipMalloc(&p, bytes));
+  return p;
+}
+
+void dev_free(void* p, hipStream_t s) {
+  if (!p) return;
+  if (g_free) {
+    g_free(p, s, g_ctx);
+    return;
+  }
+  (void)hipFree(p);
+}
+
+}  // namespace mbl
+
+using namespace mbl;
+
+extern "C" {
+
+const char* mbl_last_error(void) { return g_last_error.c_str(); }
+
+int mbl_version(void) { return 10000; }
+
+mbl_status mbl_set_allocator(mbl_alloc_fn alloc, mbl_free_fn free_fn, void* ctx) {
+  return guard([&] {
+    require((alloc == nullptr) == (free_fn == nullptr), "allocator: give both callbacks or neither");
+    g_alloc = alloc;
+    g_free = free_fn;
+    g_ctx = ctx;
+    return MBL_OK;
+  });
+}
+
+mbl_status mbl_hamiltonian_create(int L, double Sz, double J, double Delta, const double* h_host,
+                                  hipStream_t stream, mbl_ham* out) {
+  return guard([&] {
+    require(out != nullptr, "out is NULL");
+    *out = nullptr;
+    require(L >= 2 && L <= kMaxL, "L must be in [2, 32]");
+    require(std::isfinite(Sz) && std::isfinite(J) && std::isfinite(Delta), "Sz, J, Delta must be finite");
+    const double two = 2.0 * Sz;
+    require(two == std::round(two), "2*Sz must be an integer");
+    const long long tsz = (long long)std::llround(two);
+    require(((tsz + L) % 2 + 2) % 2 == 0, "2*Sz must have the parity of L");
+    require(std::fabs(Sz) <= 0.5 * L, "|Sz| must be <= L/2");
+    require(h_host != nullptr, "h is NULL");
+    for (int i = 0; i < L; ++i) require(std::isfinite(h_host[i]), "h must be finite");
+    auto* H = new Ham();
+    try {
+      H->L = L;
+      H->nup = (int)((tsz + L) / 2);
+      H->J = J;
+      H->Delta = Delta;
+      H->hsum = 0;
+      for (int i = 0; i < L; ++i) {
+        H->h[i] = h_host[i];
+        H->hsum += h_host[i];
+      }
+      const auto C = pascal_table();
+      H->n = C[L * kPascal + H->nup];
+      build_tables(*H, stream);
+      MBL_HIP(hipStreamSynchronize(stream));
+    } catch (...) {
+      delete H;
+      throw;
+    }
+    *out = reinterpret_cast<mbl_ham>(H);
+    return MBL_OK;
+  });
+}
+
+mbl_status mbl_hamiltonian_destroy(mbl_ham h) {
+  return guard([&] {
+    delete reinterpret_cast<Ham*>(h);
+    return MBL_OK;
+  });
+}
+
+mbl_status mbl_hamiltonian_dim(mbl_ham h, int64_t* n) {
+  return guard([&] {
+    require(n != nullptr, "n is NULL");
+    *n = ham(h).n;
+    return MBL_OK;
+  });
+}
+
+mbl_status mbl_sector_states(mbl_ham h, uint64_t* states_host) {
+  return guard([&] {
+    const Ham& H = ham(h);
+    require(states_host != nullptr, "states is NULL");
+    std::vector<uint32_t> tmp((size_t)H.n);
+    MBL_HIP(hipMemcpy(tmp.data(), H.states.get(), (size_t)H.n * sizeof(uint32_t), hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < H.n; ++i) states_host[i] = tmp[(size_t)i];
+    return MBL_OK;
+  });
+}
+
+mbl_status mbl_rank(mbl_ham h, const uint64_t* states_host, int64_t count, int64_t* idx_host) {
+  return guard([&] {
+    const Ham& H = ham(h);
+    require(count >= 0, "count < 0");
+    if (count == 0) return MBL_OK;
+    require(states_host && idx_host, "NULL array");
+    DevBuf q((size_t)count * sizeof(uint64_t), nullptr), r((size_t)count * sizeof(int64_t), nullptr);
+    MBL_HIP(hipMemcpy(q.get(), states_host, q.bytes(), hipMemcpyHostToDevice));
+    rank_states(H, q.as<uint64_t>(), count, r.as<int64_t>(), nullptr);
+    MBL_HIP(hipMemcpy(idx_host, r.get(), r.bytes(), hipMemcpyDeviceToHost));
+    return MBL_OK;
+  });
+}
+
+mbl_status mbl_diagonal(mbl_ham h, double sigma, double* diag_dev, double* jacobi_dev, hipStream_t s) {
+  return guard([&] {
+    const Ham& H = ham(h);
+    require(std::isfinite(sigma), "sigma must be finite");
+    if (diag_dev)
+      MBL_HIP(hipMemcpyAsync(diag_dev, H.diag.get(), (size_t)H.n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (jacobi_dev) launch_jacobi<double>(H, sigma, jacobi_dev, s);
+    return MBL_OK;
+  });
+}
+
+static void check_block(const void* X, int64_t ld, int b, const char* name) {
+  require(X != nullptr, name);
+  require(ld >= b, "leading dimension < b");
+}
+
+mbl_status mbl_apply_block(mbl_ham h, double sigma, mbl_precision prec, const void* X, int64_t ldx,
+                           void* Y, int64_t ldy, int b, hipStream_t s) {
+  return guard([&] {
+    const Ham& H = ham(h);
+    require(std::isfinite(sigma), "sigma must be finite");
+    require(block_prec(prec), "precision must be MBL_F64 or MBL_F32");
+    require(b >= 1, "b < 1");
+    check_block(X, ldx, b, "X is NULL");
+    check_block(Y, ldy, b, "Y is NULL");
+    require(X != Y, "X and Y must not overlap");
+    if (prec == MBL_F64)
+      launch_apply<double>(H, sigma, static_cast<const double*>(X), ldx, static_cast<double*>(Y), ldy, b, s);
+    else
+      launch_apply<float>(H, sigma, static_cast<const float*>(X), ldx, static_cast<float*>(Y), ldy, b, s);
+    return MBL_OK;
+  });
+}
+
+mbl_status mbl_fold_apply(mbl_ham h, double sigma, mbl_precision prec, const void* X, int64_t ldx,
+                          void* T, int64_t ldt, void* Y, int64_t ldy, int b, hipStream_t s) {
+  return guard([&] {
+    const Ham& H = ham(h);
+    require(std::isfinite(sigma), "sigma must be finite");
+    require(block_prec(prec), "precision must be MBL_F64 or MBL_F32");
+    require(b >= 1, "b < 1");
+    check_block(X, ldx, b, "X is NULL");
+    check_block(T, ldt, b, "T is NULL");
+    check_block(Y, ldy, b, "Y is NULL");
+    require(X != T && T != Y, "buffers must not overlap");
+    if (prec == MBL_F64) {
+      launch_apply<double>(H, sigma, static_cast<const double*>(X), ldx, static_cast<double*>(T), ldt, b, s);
+      launch_apply<double>(H, sigma, static_cast<const double*>(T), ldt, static_cast<double*>(Y), ldy, b, s);
+    } else {
+      launch_apply<float>(H, sigma, static_cast<const float*>(X), ldx, static_cast<float*>(T), ldt, b, s);
+      launch_apply<float>(H, sigma, static_cast<const float*>(T), ldt, static_cast<float*>(Y), ldy, b, s);
+    }
+    return MBL_OK;
+  });
+}
+
+mbl_status mbl_pcg(mbl_ham h, double sigma, mbl_precision prec, const void* R, int64_t ldr, void* W,
+                   int64_t ldw, int b, int m, hipStream_t s) {
+  return guard([&] {
+    const Ham& H = ham(h);
+    require(std::isfinite(sigma), "sigma must be finite");
+    require(block_prec(prec), "precision must be MBL_F64 or MBL_F32");
+    require(b >= 1 && m >= 0, "b < 1 or m < 0");
+    check_block(R, ldr, b, "R is NULL");
+    check_block(W, ldw, b, "W is NULL");
+    require(R != W, "R and W must not overlap");
+    if (prec == MBL_F64) {
+      DevBuf jac((size_t)H.n * sizeof(double), s);
+      launch_jacobi<double>(H, sigma, jac.as<double>(), s);
+      run_pcg<double>(H, sigma, jac.as<double>(), static_cast<const double*>(R), ldr, static_cast<double*>(W), ldw, b, m, s);
+    } else {
+      DevBuf jac((size_t)H.n * sizeof(float), s);
+      launch_jacobi<float>(H, sigma, jac.as<float>(), s);
+      run_pcg<float>(H, sigma, jac.as<float>(), static_cast<const float*>(R), ldr, static_cast<float*>(W), ldw, b, m, s);
+    }
+    return MBL_OK;
+  });
+}
+
+mbl_status mbl_gram(mbl_precision prec, int64_t n, const void* A, int64_t lda, int p, const void* B,
+                    int64_t ldb, int q, double* C_dev, int64_t ldc, hipStream_t s) {
+  return guard([&] {
+    require(block_prec(prec), "precision must be MBL_F64 or MBL_F32");
+    require(n >= 0 && p >= 1 && q >= 1, "bad sizes");
+    check_block(A, lda, p, "A is NULL");
+    check_block(B, ldb, q, "B is NULL");
+    require(C_dev != nullptr && ldc >= q, "bad C");
+    if (prec == MBL_F64)
+      launch_gram<double>(n, static_cast<const double*>(A), lda, p, static_cast<const double*>(B), ldb, q, C_dev, ldc, s);
+    else
+      launch_gram<float>(n, static_cast<const float*>(A), lda, p, static_cast<const float*>(B), ldb, q, C_dev, ldc, s);
+    return MBL_OK;
+  });
+}
+
+mbl_status mbl_block_combine(mbl_precision prec, int64_t n, const void* A, int64_t lda, int p,
+                             const double* C_dev, int64_t ldc, void* Y, int64_t ldy, int q, hipStream_t s) {
+  return guard([&] {
+    require(block_prec(prec), "precision must be MBL_F64 or MBL_F32");
+    require(n >= 0 && p >= 1 && q >= 1, "bad sizes");
+    check_block(A, lda, p, "A is NULL");
+    check_block(Y, ldy, q, "Y is NULL");
+    require(C_dev != nullptr && ldc >= q, "bad C");
+    require(A != Y, "A and Y must not overlap");
+    if (prec == MBL_F64)
+      launch_combine<double>(n, static_cast<const double*>(A), lda, p, C_dev, ldc, static_cast<double*>(Y), ldy, q, 0.0, s);
+    else
+      launch_combine<float>(n, static_cast<const float*>(A), lda, p, C_dev, ldc, static_cast<float*>(Y), ldy, q, 0.0, s);
+    return MBL_OK;
+  });
+}
+
+mbl_status mbl_small_eigh(int m, const double* A_dev, int64_t lda, double* w_dev, double* V_dev,
+                          int64_t ldv, hipStream_t s) {
+  return guard([&] {
+    require(m >= 1 && m <= 1024, "m must be in [1, 1024]");
+    require(A_dev && w_dev && V_dev, "NULL argument");
+    require(lda >= m && ldv >= m, "leading dimension < m");
+    DevBuf work(small_eigh_work_bytes(m), s);
+    small_eigh(m, A_dev, lda, w_dev, V_dev, ldv, work.as<double>(), s);
+    MBL_HIP(hipStreamSynchronize(s));
+    return MBL_OK;
+  });
+}
+
+mbl_status mbl_spectrum_bounds(mbl_ham h, double tol, double* emin, double* emax, hipStream_t s) {
+  return guard([&] {
+    const Ham& H = ham(h);
+    require(emin && emax, "NULL output");
+    require(tol >= 1e-14 && std::isfinite(tol), "tol must be >= 1e-14");
+    return spectrum_bounds(H, tol, emin, emax, s);
+  });
+}
+
+mbl_status mbl_solve_opts_default(mbl_solve_opts* o) {
+  return guard([&] {
+    require(o != nullptr, "NULL opts");
+    std::memset(o, 0, sizeof(*o));
+    o->max_iter = 400;
+    o->pcg_iters = 0;
+    o->precision = MBL_F64;
+    o->verbose = 0;
+    o->seed = 0x5eed;
+    return MBL_OK;
+  });
+}
+
+mbl_status mbl_lobpcg_solve(mbl_ham h, double sigma, int nev, int block, double tol,
+                            const mbl_solve_opts* opts, double* evals_host, double* evecs_dev,
+                            int64_t ldv, double* resid_host, mbl_solve_info* info, hipStream_t s) {
+  return guard([&] {
+    const Ham& H = ham(h);
+    require(std::isfinite(sigma), "sigma must be finite");
+    require(nev >= 1 && nev <= block, "need 1 <= nev <= block");
+    require(2 * (int64_t)block <= H.n, "need 2 * block <= n");
+    require(block <= 320, "block must be <= 320");
+    require(tol > 0 && std::isfinite(tol), "tol must be > 0");
+    require(evals_host != nullptr, "evals is NULL");
+    require(evecs_dev == nullptr || ldv >= nev, "ldv < nev");
+    mbl_solve_opts o;
+    mbl_solve_opts_default(&o);
+    if (opts) o = *opts;
+    require(o.precision == MBL_F64 || o.precision == MBL_MIXED || o.precision == MBL_PCG32,
+            "precision must be MBL_F64, MBL_MIXED or MBL_PCG32");
+    require(o.max_iter >= 0 && o.pcg_iters >= 0, "negative iteration count");
+    if (info) std::memset(info, 0, sizeof(*info));
+    return solve_interior(H, sigma, nev, block, tol, o, evals_host, evecs_dev, ldv, resid_host, info, s);
+  });
+}
+
+}  // extern "C"

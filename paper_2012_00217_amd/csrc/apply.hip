@@ -1,0 +1,553 @@
+// Matrix-free block apply Y = (H - sigma I) X (paper Sec. 3.2 and 4.1) and the
+// Jacobi-preconditioned CG on the spectral fold (H - sigma I)^2 built from it.
+//
+// Gather form (H is symmetric, so no atomics):
+//   Y[r,:] = (E(s_r) - sigma) X[r,:] + (J/2) sum_{bonds i active in s_r} X[r +- C(i,t), :]
+// with t = number of up spins below site i (see sector.hip for the identity).
+//
+// Layout: X, Y are row-major, n x b with leading dimension ld.  The columns
+// are processed in chunks; within a chunk every lane owns NV vectors of VE
+// contiguous elements (16 bytes when aligned), and G = 2^log2G lanes cover one
+// row, so a wavefront covers 64/G consecutive rows.  Consecutive rows share
+// their high bits, hence mostly the same active high bonds, which keeps the
+// bond loop coherent across the wavefront.  Every gather of one bond reads
+// G*NV*VE contiguous elements per row: whole 128-byte lines for wide chunks.
+//
+// Work distribution: row tiles of 4 waves x 64/G rows; the grid is a multiple
+// of 8 and workgroup k runs on XCD k % 8, so each XCD gets one contiguous
+// range of tiles and the low-bond neighbours (offsets C(i,t) small) of its
+// rows stay in its own L2.
+//
+// Column reductions (the CG dot products) are accumulated in FP64 per lane,
+// reduced across the wavefront with a fixed butterfly, across the 4 waves in
+// LDS, written as one partial per workgroup and folded by a separate kernel in
+// workgroup order, so every dot product is bitwise reproducible.
+#include <algorithm>
+#include <cstdlib>
+
+#include "common.h"
+
+namespace mbl {
+namespace {
+
+template <class T, int VE>
+struct alignas(sizeof(T) * VE) Pack {
+  T v[VE];
+};
+
+enum { EPI_PLAIN = 0, EPI_NORM2 = 1, EPI_PCG = 2 };
+
+template <class T>
+struct ApplyArgs {
+  const uint32_t* states;
+  const double* diag;
+  const uint32_t* pascal;
+  const T* X;
+  int64_t ldx;
+  T* Y;
+  int64_t ldy;
+  // EPI_PCG: the apply result is q = A p; x += alpha p, r -= alpha q.
+  T* x;
+  int64_t ldxv;
+  T* r;
+  int64_t ldr;
+  const T* p;
+  int64_t ldp;
+  const T* jac;
+  const PcgCoef* coef;
+  double* part;
+  int64_t n;
+  double sigma, halfJ;
+  int L;
+  int col0, w, log2G;
+  int64_t ntiles, tiles_per_xcd;
+};
+
+constexpr int kWaves = 4;
+constexpr int kThreads = 64 * kWaves;
+
+template <class T, int VE, int NV>
+__device__ inline void block_reduce_store(double (&red)[NV * VE], int log2G, int w,
+                                          double* __restrict__ part) {
+  extern __shared__ double sred[];  // [kWaves][w]
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int G = 1 << log2G;
+#pragma unroll
+  for (int k = 0; k < NV * VE; ++k)
+    for (int off = G; off < 64; off <<= 1) red[k] += __shfl_xor(red[k], off);
+  if (lane < G) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q)
+#pragma unroll
+      for (int e = 0; e < VE; ++e) sred[wave * w + (q * G + lane) * VE + e] = red[q * VE + e];
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < w; c += kThreads) {
+    double s = sred[c];
+#pragma unroll
+    for (int wv = 1; wv < kWaves; ++wv) s += sred[wv * w + c];
+    part[(int64_t)blockIdx.x * w + c] = s;
+  }
+}
+
+template <class T, int VE, int NV, int EPI>
+__global__ __launch_bounds__(kThreads) void k_apply(ApplyArgs<T> a) {
+  using P = Pack<T, VE>;
+  constexpr int BB = (NV * VE * sizeof(T) >= 32) ? 4 : 8;  // bonds per batch of loads
+  __shared__ uint32_t C[kPascal * kPascal];
+  for (int i = threadIdx.x; i < kPascal * kPascal; i += kThreads) C[i] = a.pascal[i];
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int G = 1 << a.log2G;
+  const int RW = 64 >> a.log2G;
+  const int rsub = lane >> a.log2G;
+  const int cl = lane & (G - 1);
+  const int nb = a.L - 1;
+  const uint32_t bondmask = nb > 0 ? ((1u << nb) - 1u) : 0u;
+  const int cbase = a.col0 + cl * VE;  // first column of unit 0 of this lane
+
+  double red[NV * VE];
+#pragma unroll
+  for (int k = 0; k < NV * VE; ++k) red[k] = 0.0;
+  T alpha[NV * VE];
+  if constexpr (EPI == EPI_PCG) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q)
+#pragma unroll
+      for (int e = 0; e < VE; ++e) alpha[q * VE + e] = (T)a.coef[cbase + q * G * VE + e].alpha;
+  }
+  const T hj = (T)a.halfJ;
+
+  const int xcd = blockIdx.x & 7;
+  const int slot = blockIdx.x >> 3;
+  const int nslots = gridDim.x >> 3;
+  const int64_t t_begin = (int64_t)xcd * a.tiles_per_xcd;
+  const int64_t t_end = min(t_begin + a.tiles_per_xcd, a.ntiles);
+  for (int64_t tile = t_begin + slot; tile < t_end; tile += nslots) {
+    const int64_t row = tile * (kWaves * RW) + wave * RW + rsub;
+    if (row >= a.n) continue;
+    const uint32_t s = a.states[row];
+    const uint32_t dw = (s ^ (s >> 1)) & bondmask;
+    P own[NV];
+    {
+      const T* xr = a.X + row * a.ldx + cbase;
+#pragma unroll
+      for (int q = 0; q < NV; ++q) own[q] = *reinterpret_cast<const P*>(xr + q * G * VE);
+    }
+    T nbs[NV * VE];
+#pragma unroll
+    for (int k = 0; k < NV * VE; ++k) nbs[k] = (T)0;
+    for (int i0 = 0; i0 < nb; i0 += BB) {
+      P v[BB][NV];
+      bool act[BB];
+#pragma unroll
+      for (int u = 0; u < BB; ++u) {
+        const int i = i0 + u;
+        act[u] = (i < nb) && ((dw >> i) & 1u);
+        int64_t tgt = row;
+        if (act[u]) {
+          const uint32_t t = __popc(s & ((1u << i) - 1u));
+          const int64_t c = C[i * kPascal + t];
+          tgt = ((s >> i) & 1u) ? row + c : row - c;
+          // the flip identity keeps tgt in [0, n); the guard makes a corrupted
+          // state table drop a term instead of reading out of bounds
+          act[u] = (tgt >= 0) && (tgt < a.n);
+        }
+        if (act[u]) {
+          const T* xp = a.X + tgt * a.ldx + cbase;
+#pragma unroll
+          for (int q = 0; q < NV; ++q) v[u][q] = *reinterpret_cast<const P*>(xp + q * G * VE);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < BB; ++u)
+        if (act[u]) {
+#pragma unroll
+          for (int q = 0; q < NV; ++q)
+#pragma unroll
+            for (int e = 0; e < VE; ++e) nbs[q * VE + e] += v[u][q].v[e];
+        }
+    }
+    const T ed = (T)(a.diag[row] - a.sigma);
+    T acc[NV * VE];
+#pragma unroll
+    for (int q = 0; q < NV; ++q)
+#pragma unroll
+      for (int e = 0; e < VE; ++e) acc[q * VE + e] = ed * own[q].v[e] + hj * nbs[q * VE + e];
+
+    if constexpr (EPI == EPI_PLAIN || EPI == EPI_NORM2) {
+      T* yr = a.Y + row * a.ldy + cbase;
+#pragma unroll
+      for (int q = 0; q < NV; ++q) {
+        P o;
+#pragma unroll
+        for (int e = 0; e < VE; ++e) o.v[e] = acc[q * VE + e];
+        *reinterpret_cast<P*>(yr + q * G * VE) = o;
+      }
+      if constexpr (EPI == EPI_NORM2) {
+#pragma unroll
+        for (int k = 0; k < NV * VE; ++k) red[k] += (double)acc[k] * (double)acc[k];
+      }
+    } else {  // EPI_PCG
+      const T* pr = a.p + row * a.ldp + cbase;
+      T* xr = a.x + row * a.ldxv + cbase;
+      T* rr = a.r + row * a.ldr + cbase;
+      const T dinv = (T)1 / a.jac[row];
+#pragma unroll
+      for (int q = 0; q < NV; ++q) {
+        P pv = *reinterpret_cast<const P*>(pr + q * G * VE);
+        P xv = *reinterpret_cast<const P*>(xr + q * G * VE);
+        P rv = *reinterpret_cast<const P*>(rr + q * G * VE);
+#pragma unroll
+        for (int e = 0; e < VE; ++e) {
+          const T al = alpha[q * VE + e];
+          xv.v[e] = xv.v[e] + al * pv.v[e];
+          rv.v[e] = rv.v[e] - al * acc[q * VE + e];
+          red[q * VE + e] += (double)rv.v[e] * (double)(rv.v[e] * dinv);
+        }
+        *reinterpret_cast<P*>(xr + q * G * VE) = xv;
+        *reinterpret_cast<P*>(rr + q * G * VE) = rv;
+      }
+    }
+  }
+  if constexpr (EPI != EPI_PLAIN) block_reduce_store<T, VE, NV>(red, a.log2G, a.w, a.part);
+}
+
+// PCG element-wise kernels with the same lane layout as k_apply.
+enum { ELT_INIT = 0, ELT_PUPD = 1 };
+
+template <class T>
+struct EltArgs {
+  const T* R;  // INIT: right-hand side
+  int64_t ldR;
+  T* x;
+  int64_t ldxv;
+  T* r;
+  int64_t ldr;
+  T* p;
+  int64_t ldp;
+  const T* jac;
+  const PcgCoef* coef;
+  double* part;
+  int64_t n;
+  int col0, w, log2G;
+  int64_t ntiles, tiles_per_xcd;
+};
+
+template <class T, int VE, int NV, int MODE>
+__global__ __launch_bounds__(kThreads) void k_pcg_elt(EltArgs<T> a) {
+  using P = Pack<T, VE>;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int G = 1 << a.log2G;
+  const int RW = 64 >> a.log2G;
+  const int rsub = lane >> a.log2G;
+  const int cl = lane & (G - 1);
+  const int cbase = a.col0 + cl * VE;
+  double red[NV * VE];
+#pragma unroll
+  for (int k = 0; k < NV * VE; ++k) red[k] = 0.0;
+  T beta[NV * VE];
+  bool live[NV * VE];
+  if constexpr (MODE == ELT_PUPD) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q)
+#pragma unroll
+      for (int e = 0; e < VE; ++e) {
+        const PcgCoef& c = a.coef[cbase + q * G * VE + e];
+        beta[q * VE + e] = (T)c.beta;
+        live[q * VE + e] = c.live != 0;
+      }
+  }
+  const int xcd = blockIdx.x & 7;
+  const int slot = blockIdx.x >> 3;
+  const int nslots = gridDim.x >> 3;
+  const int64_t t_begin = (int64_t)xcd * a.tiles_per_xcd;
+  const int64_t t_end = min(t_begin + a.tiles_per_xcd, a.ntiles);
+  for (int64_t tile = t_begin + slot; tile < t_end; tile += nslots) {
+    const int64_t row = tile * (kWaves * RW) + wave * RW + rsub;
+    if (row >= a.n) continue;
+    const T dinv = (T)1 / a.jac[row];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const int64_t off = cbase + q * G * VE;
+      if constexpr (MODE == ELT_INIT) {
+        P rv = *reinterpret_cast<const P*>(a.R + row * a.ldR + off);
+        P xv, pv;
+#pragma unroll
+        for (int e = 0; e < VE; ++e) {
+          xv.v[e] = (T)0;
+          pv.v[e] = rv.v[e] * dinv;
+          red[q * VE + e] += (double)rv.v[e] * (double)pv.v[e];
+        }
+        if (a.r != a.R) *reinterpret_cast<P*>(a.r + row * a.ldr + off) = rv;
+        *reinterpret_cast<P*>(a.x + row * a.ldxv + off) = xv;
+        *reinterpret_cast<P*>(a.p + row * a.ldp + off) = pv;
+      } else {
+        P rv = *reinterpret_cast<const P*>(a.r + row * a.ldr + off);
+        P pv = *reinterpret_cast<const P*>(a.p + row * a.ldp + off);
+#pragma unroll
+        for (int e = 0; e < VE; ++e)
+          if (live[q * VE + e]) pv.v[e] = rv.v[e] * dinv + beta[q * VE + e] * pv.v[e];
+        *reinterpret_cast<P*>(a.p + row * a.ldp + off) = pv;
+      }
+    }
+  }
+  if constexpr (MODE == ELT_INIT) block_reduce_store<T, VE, NV>(red, a.log2G, a.w, a.part);
+}
+
+// Fold the per-workgroup partials of one chunk (fixed order) and update the
+// CG coefficients of its columns.  One wavefront per column.
+enum { FIN_INIT = 0, FIN_ALPHA = 1, FIN_BETA = 2 };
+
+template <int MODE>
+__global__ __launch_bounds__(kThreads) void k_pcg_finalize(const double* __restrict__ part,
+                                                           int nwg, int w, int col0,
+                                                           PcgCoef* __restrict__ coef) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int c = blockIdx.x * kWaves + wave;
+  if (c >= w) return;
+  double s = 0.0;
+  for (int g = lane; g < nwg; g += 64) s += part[(int64_t)g * w + c];
+  for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
+  if (lane != 0) return;
+  PcgCoef& k = coef[col0 + c];
+  if (MODE == FIN_INIT) {
+    k.rho = s;
+    k.live = s > 0.0;
+    k.alpha = 0.0;
+    k.beta = 0.0;
+    k.pap = 0.0;
+  } else if (MODE == FIN_ALPHA) {
+    k.pap = s;
+    k.live = k.live && (s > 0.0);
+    k.alpha = k.live ? k.rho / s : 0.0;
+  } else {
+    k.live = k.live && (s > 0.0);
+    k.beta = k.live ? s / k.rho : 0.0;
+    if (k.live) k.rho = s;
+  }
+}
+
+struct Chunk {
+  int col0, w, VE, NV, log2G;
+};
+
+int env_int(const char* name, int dflt) {
+  const char* v = std::getenv(name);
+  return v ? std::atoi(v) : dflt;
+}
+
+// Split columns [0, b) into chunks of at most max_bytes per row.
+template <class T>
+std::vector<Chunk> plan_chunks(int b, bool aligned16) {
+  const int max_bytes = std::max(16, env_int("MBL_APPLY_CHUNK_BYTES", 512));
+  std::vector<Chunk> out;
+  const int VEv = aligned16 ? (int)(16 / sizeof(T)) : 1;
+  int c = 0;
+  while (c < b) {
+    int VE = VEv;
+    int units = (b - c) / VE;
+    if (units == 0) {
+      VE = 1;
+      units = b - c;
+    }
+    const int NV = units >= 4 ? 4 : (units >= 2 ? 2 : 1);
+    int G = std::min(64, units / NV);
+    G = std::min(G, std::max(1, max_bytes / (int)(NV * VE * sizeof(T))));
+    int log2G = 0;
+    while ((2 << log2G) <= G) ++log2G;
+    G = 1 << log2G;
+    out.push_back({c, G * NV * VE, VE, NV, log2G});
+    c += G * NV * VE;
+  }
+  return out;
+}
+
+bool al16(const void* p, int64_t ld, size_t es) {
+  return (reinterpret_cast<uintptr_t>(p) % 16 == 0) && ((ld * (int64_t)es) % 16 == 0);
+}
+
+struct Grid {
+  int64_t ntiles, tiles_per_xcd;
+  unsigned nwg;
+};
+
+Grid make_grid(int64_t n, int log2G) {
+  const int64_t rows_per_tile = kWaves * (64 >> log2G);
+  Grid g;
+  g.ntiles = (n + rows_per_tile - 1) / rows_per_tile;
+  g.tiles_per_xcd = (g.ntiles + 7) / 8;
+  const int64_t max_slots = std::min(256, std::max(1, env_int("MBL_APPLY_SLOTS_PER_XCD", 256)));
+  const int64_t slots = std::min<int64_t>(g.tiles_per_xcd, max_slots);
+  g.nwg = (unsigned)(8 * std::max<int64_t>(1, slots));
+  return g;
+}
+
+constexpr int kMaxWg = 8 * 256;  // upper bound of Grid::nwg with the default knob
+
+template <class T, int EPI>
+void dispatch_apply(const Chunk& ch, const Grid& g, ApplyArgs<T> a, hipStream_t s) {
+  a.col0 = ch.col0;
+  a.w = ch.w;
+  a.log2G = ch.log2G;
+  a.ntiles = g.ntiles;
+  a.tiles_per_xcd = g.tiles_per_xcd;
+  const size_t shm = (EPI == EPI_PLAIN) ? 0 : (size_t)kWaves * ch.w * sizeof(double);
+  constexpr int VV = 16 / sizeof(T);
+#define MBL_APPLY_CASE(VE_, NV_)                                                             \
+  if (ch.VE == VE_ && ch.NV == NV_) {                                                       \
+    hipLaunchKernelGGL((k_apply<T, VE_, NV_, EPI>), dim3(g.nwg), dim3(kThreads), shm, s, a); \
+    MBL_CHECK_LAUNCH();                                                                     \
+    return;                                                                                 \
+  }
+  MBL_APPLY_CASE(VV, 4)
+  MBL_APPLY_CASE(VV, 2)
+  MBL_APPLY_CASE(VV, 1)
+  MBL_APPLY_CASE(1, 4)
+  MBL_APPLY_CASE(1, 2)
+  MBL_APPLY_CASE(1, 1)
+#undef MBL_APPLY_CASE
+  fail(MBL_EINTERNAL, "apply: no kernel for chunk shape");
+}
+
+template <class T, int MODE>
+void dispatch_elt(const Chunk& ch, const Grid& g, EltArgs<T> a, hipStream_t s) {
+  a.col0 = ch.col0;
+  a.w = ch.w;
+  a.log2G = ch.log2G;
+  a.ntiles = g.ntiles;
+  a.tiles_per_xcd = g.tiles_per_xcd;
+  const size_t shm = (MODE == ELT_INIT) ? (size_t)kWaves * ch.w * sizeof(double) : 0;
+  constexpr int VV = 16 / sizeof(T);
+#define MBL_ELT_CASE(VE_, NV_)                                                                 \
+  if (ch.VE == VE_ && ch.NV == NV_) {                                                         \
+    hipLaunchKernelGGL((k_pcg_elt<T, VE_, NV_, MODE>), dim3(g.nwg), dim3(kThreads), shm, s, a); \
+    MBL_CHECK_LAUNCH();                                                                       \
+    return;                                                                                   \
+  }
+  MBL_ELT_CASE(VV, 4)
+  MBL_ELT_CASE(VV, 2)
+  MBL_ELT_CASE(VV, 1)
+  MBL_ELT_CASE(1, 4)
+  MBL_ELT_CASE(1, 2)
+  MBL_ELT_CASE(1, 1)
+#undef MBL_ELT_CASE
+  fail(MBL_EINTERNAL, "pcg: no kernel for chunk shape");
+}
+
+template <int MODE>
+void finalize(const Chunk& ch, const Grid& g, const double* part, PcgCoef* coef, hipStream_t s) {
+  hipLaunchKernelGGL(k_pcg_finalize<MODE>, dim3((ch.w + kWaves - 1) / kWaves), dim3(kThreads), 0,
+                     s, part, (int)g.nwg, ch.w, ch.col0, coef);
+  MBL_CHECK_LAUNCH();
+}
+
+template <class T>
+ApplyArgs<T> base_args(const Ham& H, double sigma) {
+  ApplyArgs<T> a{};
+  a.states = H.states.as<uint32_t>();
+  a.diag = H.diag.as<double>();
+  a.pascal = H.pascal.as<uint32_t>();
+  a.n = H.n;
+  a.sigma = sigma;
+  a.halfJ = 0.5 * H.J;
+  a.L = H.L;
+  return a;
+}
+
+}  // namespace
+
+template <class T>
+void launch_apply(const Ham& H, double sigma, const T* X, int64_t ldx, T* Y, int64_t ldy, int w,
+                  hipStream_t s) {
+  if (H.n == 0 || w == 0) return;
+  const bool aligned = al16(X, ldx, sizeof(T)) && al16(Y, ldy, sizeof(T));
+  ApplyArgs<T> a = base_args<T>(H, sigma);
+  a.X = X;
+  a.ldx = ldx;
+  a.Y = Y;
+  a.ldy = ldy;
+  for (const Chunk& ch : plan_chunks<T>(w, aligned))
+    dispatch_apply<T, EPI_PLAIN>(ch, make_grid(H.n, ch.log2G), a, s);
+}
+
+// Block Jacobi-PCG on A = (H - sigma)^2, x0 = 0, m steps, per column:
+//   r = R, p = M^-1 r, rho = r.M^-1 r
+//   repeat: T = (H-sigma) p ; alpha = rho / |T|^2          (p.A p = |T|^2)
+//           q = (H-sigma) T ; x += alpha p ; r -= alpha q ; rho' = r.M^-1 r
+//           beta = rho'/rho ; p = M^-1 r + beta p
+// Every coefficient stays on the device; no host synchronisation inside.
+template <class T>
+void run_pcg(const Ham& H, double sigma, const T* jac, const T* R, int64_t ldr, T* W, int64_t ldw,
+             int b, int m, hipStream_t s) {
+  const int64_t n = H.n;
+  if (n == 0 || b == 0) return;
+  DevBuf rbuf((size_t)n * b * sizeof(T), s), pbuf((size_t)n * b * sizeof(T), s),
+      tbuf((size_t)n * b * sizeof(T), s);
+  DevBuf part((size_t)kMaxWg * std::min(b, 4096) * sizeof(double) + 64, s);
+  DevBuf coefb((size_t)b * sizeof(PcgCoef), s);
+  T* r = rbuf.as<T>();
+  T* p = pbuf.as<T>();
+  T* t = tbuf.as<T>();
+  PcgCoef* coef = coefb.as<PcgCoef>();
+  const bool aligned = al16(R, ldr, sizeof(T)) && al16(W, ldw, sizeof(T)) && al16(r, b, sizeof(T));
+  const auto chunks = plan_chunks<T>(b, aligned);
+  for (const Chunk& ch : chunks) {
+    if ((size_t)ch.w * kMaxWg * sizeof(double) > part.bytes()) fail(MBL_EINTERNAL, "pcg: part");
+    const Grid g = make_grid(n, ch.log2G);
+    EltArgs<T> e{};
+    e.R = R;
+    e.ldR = ldr;
+    e.x = W;
+    e.ldxv = ldw;
+    e.r = r;
+    e.ldr = b;
+    e.p = p;
+    e.ldp = b;
+    e.jac = jac;
+    e.coef = coef;
+    e.part = part.as<double>();
+    e.n = n;
+    dispatch_elt<T, ELT_INIT>(ch, g, e, s);
+    finalize<FIN_INIT>(ch, g, part.as<double>(), coef, s);
+
+    ApplyArgs<T> a1 = base_args<T>(H, sigma);  // T = (H - sigma) p, |T|^2
+    a1.X = p;
+    a1.ldx = b;
+    a1.Y = t;
+    a1.ldy = b;
+    a1.part = part.as<double>();
+    ApplyArgs<T> a2 = base_args<T>(H, sigma);  // q = (H - sigma) T, CG update
+    a2.X = t;
+    a2.ldx = b;
+    a2.x = W;
+    a2.ldxv = ldw;
+    a2.r = r;
+    a2.ldr = b;
+    a2.p = p;
+    a2.ldp = b;
+    a2.jac = jac;
+    a2.coef = coef;
+    a2.part = part.as<double>();
+    for (int it = 0; it < m; ++it) {
+      dispatch_apply<T, EPI_NORM2>(ch, g, a1, s);
+      finalize<FIN_ALPHA>(ch, g, part.as<double>(), coef, s);
+      dispatch_apply<T, EPI_PCG>(ch, g, a2, s);
+      finalize<FIN_BETA>(ch, g, part.as<double>(), coef, s);
+      dispatch_elt<T, ELT_PUPD>(ch, g, e, s);
+    }
+  }
+  MBL_HIP(hipStreamSynchronize(s));  // work buffers are freed on return
+}
+
+template void launch_apply<double>(const Ham&, double, const double*, int64_t, double*, int64_t,
+                                   int, hipStream_t);
+template void launch_apply<float>(const Ham&, double, const float*, int64_t, float*, int64_t, int,
+                                  hipStream_t);
+template void run_pcg<double>(const Ham&, double, const double*, const double*, int64_t, double*,
+                              int64_t, int, int, hipStream_t);
+template void run_pcg<float>(const Ham&, double, const float*, const float*, int64_t, float*,
+                             int64_t, int, int, hipStream_t);
+
+}  // namespace mbl

@@ -1,0 +1,275 @@
+// Tall-skinny block kernels of LOBPCG (paper Sec. 3.2, property (ii): a block
+// method turns the work into matrix-matrix operations).
+//
+//  * Gram products C = A^T B of n x p and n x q blocks on the matrix cores:
+//    v_mfma_f64_16x16x4f64 for FP64 blocks, v_mfma_f32_16x16x4f32 with FP32
+//    accumulation for FP32 blocks.  The n dimension is split over workgroups;
+//    each writes an FP64 partial tile and a second kernel folds the partials
+//    in split order, so the result is bitwise reproducible.
+//  * Block combination Y = A C + beta Y with a small FP64 coefficient matrix
+//    C (rounded to the block type), register-tiled through LDS.
+//  * Precision conversion and the counter-based random starting block.
+#include <algorithm>
+
+#include "common.h"
+
+namespace mbl {
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <class T>
+struct Mfma;
+// Output row of element v held by lane group g = lane / 16 (column = lane % 16):
+// the FP64 instruction interleaves the four lane groups row by row, the FP32
+// one gives each lane group four consecutive rows.
+template <>
+struct Mfma<double> {
+  using acc = d4;
+  __device__ static acc op(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int g, int v) { return g + 4 * v; }
+};
+template <>
+struct Mfma<float> {
+  using acc = f4;
+  __device__ static acc op(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int g, int v) { return 4 * g + v; }
+};
+
+// One workgroup = 4 waves = a 64 x 64 tile of C; wave (wy, wx) owns the
+// 32 x 32 quadrant as 2 x 2 blocks of 16 x 16.  16 x 16 x 4 MFMA operand
+// layout: lane l supplies A[i = l % 16][k = l / 16] and B[k = l / 16][j = l % 16];
+// it receives D[Mfma<T>::row(l / 16, v)][l % 16], v = 0..3.  For C = A^T B the MFMA A
+// operand is the transpose of the block, so both operands read 4 rows x 16
+// consecutive columns of the row-major blocks.
+template <class T>
+__global__ __launch_bounds__(256) void k_gram(int64_t n, const T* __restrict__ A, int64_t lda,
+                                              int p, const T* __restrict__ B, int64_t ldb, int q,
+                                              int64_t rows_per_split, double* __restrict__ part) {
+  using M = Mfma<T>;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wy = wave >> 1, wx = wave & 1;
+  const int tiles_q = (q + 63) / 64;
+  const int ty = blockIdx.x / tiles_q, tx = blockIdx.x % tiles_q;
+  const int c0 = ty * 64 + wy * 32, d0 = tx * 64 + wx * 32;
+  const int li = lane & 15, lk = lane >> 4;
+  const int64_t kb = (int64_t)blockIdx.y * rows_per_split;
+  const int64_t ke = min(n, kb + rows_per_split);
+  int ca[2], cb[2];
+  bool oka[2], okb[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    ca[u] = c0 + 16 * u + li;
+    cb[u] = d0 + 16 * u + li;
+    oka[u] = ca[u] < p;
+    okb[u] = cb[u] < q;
+  }
+  typename M::acc acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = typename M::acc{0, 0, 0, 0};
+  for (int64_t k = kb; k < ke; k += 16) {
+    T a[4][2], b[4][2];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t row = k + 4 * u + lk;
+      const bool ok = row < ke;
+#pragma unroll
+      for (int v = 0; v < 2; ++v) {
+        a[u][v] = (ok && oka[v]) ? A[row * lda + ca[v]] : (T)0;
+        b[u][v] = (ok && okb[v]) ? B[row * ldb + cb[v]] : (T)0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = M::op(a[u][i], b[u][j], acc[i][j]);
+  }
+  double* out = part + (int64_t)blockIdx.y * p * q;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = c0 + 16 * i + M::row(lk, v);
+        const int c = d0 + 16 * j + li;
+        if (r < p && c < q) out[(int64_t)r * q + c] = (double)acc[i][j][v];
+      }
+}
+
+__global__ __launch_bounds__(256) void k_gram_fold(const double* __restrict__ part, int splits,
+                                                   int p, int q, double* __restrict__ C,
+                                                   int64_t ldc) {
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)p * q) return;
+  double s = 0.0;
+  for (int sp = 0; sp < splits; ++sp) s += part[(int64_t)sp * p * q + idx];
+  C[(idx / q) * ldc + idx % q] = s;
+}
+
+// Y[r, j] = sum_k A[r, k] C[k, j] + beta Y[r, j].  Tile: 64 rows x 64 columns
+// per workgroup, 32-deep K slices in LDS; each thread owns 4 x 4 outputs.
+template <class T>
+__global__ __launch_bounds__(256) void k_combine(int64_t n, const T* __restrict__ A, int64_t lda,
+                                                 int p, const double* __restrict__ Cm,
+                                                 int64_t ldc, T* __restrict__ Y, int64_t ldy,
+                                                 int q, double beta) {
+  __shared__ T As[32][64 + 1];  // [k][row]
+  __shared__ T Cs[32][64];      // [k][col]
+  const int tid = threadIdx.x;
+  const int64_t r0 = (int64_t)blockIdx.x * 64;
+  const int c0 = blockIdx.y * 64;
+  const int tr = (tid >> 4) * 4, tc = (tid & 15) * 4;
+  T acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = (T)0;
+  for (int k0 = 0; k0 < p; k0 += 32) {
+    for (int e = tid; e < 32 * 64; e += 256) {
+      const int rr = e >> 5, kk = e & 31;  // coalesced along k within a row
+      const int64_t row = r0 + rr;
+      const int col = k0 + kk;
+      As[kk][rr] = (row < n && col < p) ? A[row * lda + col] : (T)0;
+      const int ck = e >> 6, cc = e & 63;
+      Cs[ck][cc] = (k0 + ck < p && c0 + cc < q) ? (T)Cm[(int64_t)(k0 + ck) * ldc + c0 + cc] : (T)0;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int kk = 0; kk < 32; ++kk) {
+      T av[4], cv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) av[i] = As[kk][tr + i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) cv[j] = Cs[kk][tc + j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] += av[i] * cv[j];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t row = r0 + tr + i;
+    if (row >= n) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int col = c0 + tc + j;
+      if (col >= q) continue;
+      T* y = Y + row * ldy + col;
+      *y = (beta == 0.0) ? acc[i][j] : (T)(acc[i][j] + (T)beta * *y);
+    }
+  }
+}
+
+template <class S, class D>
+__global__ __launch_bounds__(256) void k_convert(int64_t n, int b, const S* __restrict__ X,
+                                                 int64_t ldx, D* __restrict__ Y, int64_t ldy) {
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= n * b) return;
+  const int64_t r = idx / b;
+  const int c = (int)(idx % b);
+  Y[r * ldy + c] = (D)X[r * ldx + c];
+}
+
+// splitmix64 (Steele, Lea, Flood 2014) of a counter, then Box-Muller.
+__device__ inline uint64_t splitmix64(uint64_t z) {
+  z += 0x9e3779b97f4a7c15ull;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_randn(int64_t n, int b, uint64_t seed, T* __restrict__ X,
+                                               int64_t ldx) {
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= n * b) return;
+  const uint64_t h1 = splitmix64(seed ^ splitmix64(2 * (uint64_t)idx));
+  const uint64_t h2 = splitmix64(seed ^ splitmix64(2 * (uint64_t)idx + 1));
+  const double u1 = ((h1 >> 11) + 1) * (1.0 / 9007199254740993.0);  // (0, 1]
+  const double u2 = (h2 >> 11) * (1.0 / 9007199254740992.0);
+  X[(idx / b) * ldx + idx % b] = (T)(sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2));
+}
+
+inline unsigned g1(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+
+template <class T>
+void launch_gram(int64_t n, const T* A, int64_t lda, int p, const T* B, int64_t ldb, int q,
+                 double* C, int64_t ldc, hipStream_t s) {
+  if (p == 0 || q == 0) return;
+  const int tiles = ((p + 63) / 64) * ((q + 63) / 64);
+  int64_t splits = std::max<int64_t>(1, 1024 / tiles);
+  splits = std::min<int64_t>(splits, std::max<int64_t>(1, (n + 255) / 256));
+  int64_t rows = (n + splits - 1) / splits;
+  rows = ((rows + 15) / 16) * 16;
+  splits = std::max<int64_t>(1, (n + rows - 1) / rows);
+  DevBuf part((size_t)splits * p * q * sizeof(double), s);
+  if (n > 0) {
+    hipLaunchKernelGGL(k_gram<T>, dim3(tiles, (unsigned)splits), dim3(256), 0, s, n, A, lda, p, B,
+                       ldb, q, rows, part.as<double>());
+    MBL_CHECK_LAUNCH();
+  } else {
+    MBL_HIP(hipMemsetAsync(part.get(), 0, part.bytes(), s));
+  }
+  hipLaunchKernelGGL(k_gram_fold, dim3(g1((int64_t)p * q)), dim3(256), 0, s, part.as<double>(),
+                     (int)splits, p, q, C, ldc);
+  MBL_CHECK_LAUNCH();
+  MBL_HIP(hipStreamSynchronize(s));  // `part` is released on return
+}
+
+template <class T>
+void launch_combine(int64_t n, const T* A, int64_t lda, int p, const double* C, int64_t ldc, T* Y,
+                    int64_t ldy, int q, double beta, hipStream_t s) {
+  if (n == 0 || q == 0) return;
+  hipLaunchKernelGGL(k_combine<T>, dim3((unsigned)((n + 63) / 64), (unsigned)((q + 63) / 64)),
+                     dim3(256), 0, s, n, A, lda, p, C, ldc, Y, ldy, q, beta);
+  MBL_CHECK_LAUNCH();
+}
+
+template <class S, class D>
+void launch_convert(int64_t n, int b, const S* X, int64_t ldx, D* Y, int64_t ldy, hipStream_t s) {
+  if (n * b == 0) return;
+  hipLaunchKernelGGL((k_convert<S, D>), dim3(g1(n * b)), dim3(256), 0, s, n, b, X, ldx, Y, ldy);
+  MBL_CHECK_LAUNCH();
+}
+
+template <class T>
+void launch_randn(int64_t n, int b, uint64_t seed, T* X, int64_t ldx, hipStream_t s) {
+  if (n * b == 0) return;
+  hipLaunchKernelGGL(k_randn<T>, dim3(g1(n * b)), dim3(256), 0, s, n, b, seed, X, ldx);
+  MBL_CHECK_LAUNCH();
+}
+
+template void launch_gram<double>(int64_t, const double*, int64_t, int, const double*, int64_t,
+                                  int, double*, int64_t, hipStream_t);
+template void launch_gram<float>(int64_t, const float*, int64_t, int, const float*, int64_t, int,
+                                 double*, int64_t, hipStream_t);
+template void launch_combine<double>(int64_t, const double*, int64_t, int, const double*, int64_t,
+                                     double*, int64_t, int, double, hipStream_t);
+template void launch_combine<float>(int64_t, const float*, int64_t, int, const double*, int64_t,
+                                    float*, int64_t, int, double, hipStream_t);
+template void launch_convert<double, float>(int64_t, int, const double*, int64_t, float*, int64_t,
+                                            hipStream_t);
+template void launch_convert<float, double>(int64_t, int, const float*, int64_t, double*, int64_t,
+                                            hipStream_t);
+template void launch_convert<double, double>(int64_t, int, const double*, int64_t, double*,
+                                             int64_t, hipStream_t);
+template void launch_convert<float, float>(int64_t, int, const float*, int64_t, float*, int64_t,
+                                           hipStream_t);
+template void launch_randn<double>(int64_t, int, uint64_t, double*, int64_t, hipStream_t);
+template void launch_randn<float>(int64_t, int, uint64_t, float*, int64_t, hipStream_t);
+
+}  // namespace mbl

@@ -1,0 +1,148 @@
+// Internal declarations shared by the HIP sources of libmbl.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/mbl.h"
+
+namespace mbl {
+
+constexpr int kMaxL = 32;
+constexpr int kPascal = kMaxL + 1;  // C(i, t) for 0 <= i, t <= 32
+
+// Internal failure carrying the ABI status; caught at the C boundary.
+struct Error : std::runtime_error {
+  mbl_status status;
+  Error(mbl_status s, const std::string& m) : std::runtime_error(m), status(s) {}
+};
+
+[[noreturn]] inline void fail(mbl_status s, const std::string& m) { throw Error(s, m); }
+
+#define MBL_HIP(call)                                                             \
+  do {                                                                            \
+    hipError_t e_ = (call);                                                       \
+    if (e_ != hipSuccess)                                                         \
+      ::mbl::fail(e_ == hipErrorOutOfMemory ? MBL_ENOMEM : MBL_EDEVICE,           \
+                  std::string(#call) + ": " + hipGetErrorString(e_));             \
+  } while (0)
+
+#define MBL_CHECK_LAUNCH() MBL_HIP(hipGetLastError())
+
+// Device allocation through the installed callback (or hipMalloc).
+void* dev_alloc(size_t bytes, hipStream_t s);
+void dev_free(void* p, hipStream_t s);
+
+// Owning device buffer.
+class DevBuf {
+ public:
+  DevBuf() = default;
+  DevBuf(size_t bytes, hipStream_t s) : s_(s) { reset(bytes, s); }
+  ~DevBuf() { release(); }
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p_(o.p_), n_(o.n_), s_(o.s_) { o.p_ = nullptr; o.n_ = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) { release(); p_ = o.p_; n_ = o.n_; s_ = o.s_; o.p_ = nullptr; o.n_ = 0; }
+    return *this;
+  }
+  void reset(size_t bytes, hipStream_t s) {
+    release();
+    s_ = s;
+    if (bytes) p_ = dev_alloc(bytes, s);
+    n_ = bytes;
+  }
+  void release() {
+    if (p_) dev_free(p_, s_);
+    p_ = nullptr;
+    n_ = 0;
+  }
+  template <class T> T* as() const { return static_cast<T*>(p_); }
+  void* get() const { return p_; }
+  size_t bytes() const { return n_; }
+
+ private:
+  void* p_ = nullptr;
+  size_t n_ = 0;
+  hipStream_t s_ = nullptr;
+};
+
+// Per-sector Hamiltonian data (the opaque mbl_ham).
+struct Ham {
+  int L = 0, nup = 0;
+  int64_t n = 0;
+  double J = 1, Delta = 1;
+  double h[kMaxL] = {};
+  double hsum = 0;
+  DevBuf pascal;   // uint32 C[33][33]
+  DevBuf states;   // uint32 [n]
+  DevBuf diag;     // double [n]  <s|H|s>
+  DevBuf diag32;   // float  [n]  (same values rounded)
+  std::vector<uint32_t> pascal_host;
+};
+
+// Host Pascal table C[i][t] (row-major, 33 x 33), 0 where t > i.
+std::vector<uint32_t> pascal_table();
+
+// ---- kernels shared between translation units ------------------------------
+
+// Device-side column state of the block PCG (per column j).
+struct PcgCoef {
+  double rho, pap, alpha, beta;
+  int live;
+  int pad;
+};
+
+// Apply launcher: Y = (H - sigma) X over columns [0, w).
+template <class T>
+void launch_apply(const Ham& H, double sigma, const T* X, int64_t ldx, T* Y, int64_t ldy, int w,
+                  hipStream_t s);
+
+// PCG: W = PCG_m(R) (columns independent) with Jacobi diagonal jac.
+template <class T>
+void run_pcg(const Ham& H, double sigma, const T* jac, const T* R, int64_t ldr, T* W, int64_t ldw,
+             int b, int m, hipStream_t s);
+
+// Jacobi diagonal of the fold, d = (E - sigma)^2 + (J/2)^2 * (#active bonds).
+template <class T>
+void launch_jacobi(const Ham& H, double sigma, T* out, hipStream_t s);
+
+// Gram C = A^T B (FP64 p x q, row-major ldc) with deterministic reduction.
+template <class T>
+void launch_gram(int64_t n, const T* A, int64_t lda, int p, const T* B, int64_t ldb, int q,
+                 double* C, int64_t ldc, hipStream_t s);
+
+// Y = A C (+ beta Y), C FP64 (p x q).
+template <class T>
+void launch_combine(int64_t n, const T* A, int64_t lda, int p, const double* C, int64_t ldc, T* Y,
+                    int64_t ldy, int q, double beta, hipStream_t s);
+
+// Small dense (single workgroup) FP64 kernels; matrices row-major.
+void small_eigh(int m, const double* A, int64_t lda, double* w, double* V, int64_t ldv,
+                double* work, hipStream_t s);
+
+// Workspace bytes needed by small_eigh for size m.
+size_t small_eigh_work_bytes(int m);
+
+template <class S, class D>
+void launch_convert(int64_t n, int b, const S* X, int64_t ldx, D* Y, int64_t ldy, hipStream_t s);
+template <class T>
+void launch_randn(int64_t n, int b, uint64_t seed, T* X, int64_t ldx, hipStream_t s);
+
+// Builds the Pascal table, state list and diagonal of H (device).
+void build_tables(Ham& H, hipStream_t s);
+// Row index of each 64-bit state (device arrays), -1 if not in the sector.
+void rank_states(const Ham& H, const uint64_t* q_dev, int64_t cnt, int64_t* out_dev,
+                 hipStream_t s);
+
+mbl_status solve_interior(const Ham& H, double sigma, int nev, int b, double tol,
+                          const mbl_solve_opts& o, double* evals, double* evecs, int64_t ldv,
+                          double* resid, mbl_solve_info* info, hipStream_t s);
+mbl_status spectrum_bounds(const Ham& H, double tol, double* emin, double* emax, hipStream_t s);
+
+}  // namespace mbl

@@ -1,0 +1,606 @@
+// LOBPCG on the spectral fold (H - sigma I)^2 with a Jacobi-PCG
+// preconditioner (paper Sec. 3.2), and on +-H for the spectrum bounds.
+//
+// Iteration (orthonormal-basis form; the paper defers the LOBPCG details to
+// its references, these choices are standard):
+//   S = [X | P | W], kept orthonormal: X, P orthonormal and mutually
+//   orthogonal; W = PCG_m(A X - X mu) is orthogonalised against [X P] twice and
+//   orthonormalised by Cholesky-QR applied twice, with linearly dependent
+//   columns dropped.
+//   Rayleigh-Ritz on A = (H - sigma)^2: the projected matrix is the Gram of
+//   HS = (H - sigma) S, M = HS^T HS = S^T A S.  Forming it from (H - sigma) S
+//   rather than from A S keeps the tiny eigenvalues of the fold accurate to
+//   the precision of (H - sigma) S itself.
+//   X' = S C (b smallest Ritz pairs), P' = S C^ with C^ the X-free part of C
+//   made orthogonal to C and orthonormal in the small space, so
+//   [X' P'] is orthonormal without touching the n-length blocks again.
+//   Convergence: Rayleigh-Ritz with H itself inside span(X) gives the Ritz
+//   values theta of H - sigma; the nev with smallest |theta| are the wanted
+//   pairs, accepted when ||(H - sigma) x - theta x||_2 <= tol.  Before
+//   returning, the residuals are recomputed with a fresh FP64 apply.
+//
+// Precision (MBL_MIXED): a first phase keeps every n-length block in FP32 (FP32
+// applies, FP32 combinations, FP32-MFMA Grams, FP32 PCG) while all small dense
+// algebra stays FP64; once the FP32 floor is reached the blocks are promoted
+// to FP64 and the iteration continues with FP64 blocks and FP32 PCG until the
+// requested tolerance.  MBL_PCG32 runs only the second kind of phase,
+// MBL_F64 runs FP64 everywhere.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+
+#include "common.h"
+
+namespace mbl {
+
+int chol_drop(int b, const double* G, int64_t ldg, double tol, double* Rinv, double* work,
+              int* dcount, hipStream_t s);
+void small_gemm(int M, int N, int K, double alpha, const double* A, int64_t lda, bool ta,
+                const double* B, int64_t ldb, bool tb, double beta, double* C, int64_t ldc,
+                hipStream_t s);
+void select_nearest(int b, int nev, const double* theta, int* sel, hipStream_t s);
+void gather_cols(int rows, int nsel, const int* sel, const double* Z, int64_t ldz, double* out,
+                 int64_t ldo, hipStream_t s);
+
+namespace {
+
+using clk = std::chrono::steady_clock;
+double secs(clk::time_point a) { return std::chrono::duration<double>(clk::now() - a).count(); }
+
+struct Params {
+  double sigma = 0;
+  int nev = 1, b = 2;
+  double tol = 1e-10;
+  int max_iter = 400;
+  int pcg_iters = 0;
+  int verbose = 0;
+  uint64_t seed = 0;
+  bool fold = true;   // false: plain LOBPCG on sign * (H - sigma)
+  double sign = 1.0;
+};
+
+struct Stats {
+  int iters = 0, iters_fp64 = 0;
+  int64_t applies = 0, pcg_steps = 0;
+  double t_pcg = 0, t_rr = 0;
+};
+
+// Small FP64 device workspace of one solve (sizes for m = 3b).
+struct Small {
+  DevBuf M, V, w, C, Ch, T1, T2, Rinv, cw, ew, sel, cnt, K, Z, th, Zs;
+  int mmax;
+  Small(int b, hipStream_t s) {
+    const int m = 3 * b;
+    mmax = m;
+    const size_t mm = (size_t)m * m * sizeof(double);
+    M.reset(mm, s);
+    V.reset(mm, s);
+    w.reset(m * sizeof(double), s);
+    C.reset(mm, s);
+    Ch.reset(mm, s);
+    T1.reset(mm, s);
+    T2.reset(mm, s);
+    Rinv.reset(mm, s);
+    cw.reset(mm, s);
+    ew.reset(small_eigh_work_bytes(m), s);
+    sel.reset(m * sizeof(int), s);
+    cnt.reset(64, s);
+    K.reset(mm, s);
+    Z.reset(mm, s);
+    th.reset(m * sizeof(double), s);
+    Zs.reset(mm, s);
+  }
+};
+
+template <class TB>
+struct PhaseBufs {
+  int64_t n;
+  int b, ld;
+  DevBuf S[2], HS[2], R, tmp;
+  PhaseBufs(int64_t n_, int b_, hipStream_t s) : n(n_), b(b_), ld(3 * b_) {
+    for (int i = 0; i < 2; ++i) {
+      S[i].reset((size_t)n * ld * sizeof(TB), s);
+      HS[i].reset((size_t)n * ld * sizeof(TB), s);
+    }
+    R.reset((size_t)n * b * sizeof(TB), s);
+    tmp.reset((size_t)n * b * sizeof(TB), s);
+  }
+};
+
+int default_pcg_iters(int64_t n) {
+  const double m = 20.0 * std::pow((double)n / 924.0, 0.61);
+  return (int)std::max(5.0, std::min(20000.0, std::round(m)));
+}
+
+template <class TB>
+double drop_tol() {
+  return sizeof(TB) == 8 ? 1e-14 : 1e-6;
+}
+
+// Y (n x q, ld ldy) <- cols of a block: copy helper
+template <class TB>
+void copy_cols(int64_t n, int q, const TB* X, int64_t ldx, TB* Y, int64_t ldy, hipStream_t s) {
+  if (n == 0 || q == 0) return;
+  MBL_HIP(hipMemcpy2DAsync(Y, ldy * sizeof(TB), X, ldx * sizeof(TB), q * sizeof(TB), n,
+                           hipMemcpyDeviceToDevice, s));
+}
+
+template <class TB>
+class Phase {
+ public:
+  Phase(const Ham& H, const Params& p, Small& sm, Stats& st, hipStream_t s)
+      : H_(H), p_(p), sm_(sm), st_(st), s_(s), B_(H.n, p.b, s) {}
+
+  // Orthonormalise X in place (two Cholesky-QR passes); returns kept width.
+  int cholqr2(TB* X, int64_t ldx, int q) {
+    for (int pass = 0; pass < 2 && q > 0; ++pass) {
+      launch_gram<TB>(H_.n, X, ldx, q, X, ldx, q, sm_.T1.as<double>(), q, s_);
+      const int k = chol_drop(q, sm_.T1.as<double>(), q, drop_tol<TB>(), sm_.Rinv.as<double>(),
+                              sm_.cw.as<double>(), sm_.cnt.as<int>(), s_);
+      // Rinv is q x q with ld q, first k columns meaningful
+      launch_combine<TB>(H_.n, X, ldx, q, sm_.Rinv.as<double>(), q, B_.tmp.template as<TB>(), p_.b,
+                         k, 0.0, s_);
+      copy_cols<TB>(H_.n, k, B_.tmp.template as<TB>(), p_.b, X, ldx, s_);
+      q = k;
+    }
+    return q;
+  }
+
+  void apply(const TB* X, int64_t ldx, TB* Y, int64_t ldy, int q) {
+    launch_apply<TB>(H_, p_.fold ? p_.sigma : 0.0, X, ldx, Y, ldy, q, s_);
+    st_.applies += 1;
+  }
+
+  // Start from X0 (n x b).  RR on span(X0).
+  void init(const TB* X0, int64_t ldx0) {
+    const int b = p_.b;
+    TB* S = B_.S[cur_].template as<TB>();
+    TB* HS = B_.HS[cur_].template as<TB>();
+    copy_cols<TB>(H_.n, b, X0, ldx0, S, B_.ld, s_);
+    const int k = cholqr2(S, B_.ld, b);
+    if (k < b) fail(MBL_EBREAKDOWN, "starting block is rank deficient");
+    apply(S, B_.ld, HS, B_.ld, b);
+    bp_ = 0;
+    rr(b);
+  }
+
+  // Rayleigh-Ritz on span(S[:, 0:mact]); updates X, P (and HX, HP), mu.
+  void rr(int mact) {
+    const int b = p_.b;
+    const int64_t n = H_.n;
+    const auto t0 = clk::now();
+    TB* S = B_.S[cur_].template as<TB>();
+    TB* HS = B_.HS[cur_].template as<TB>();
+    TB* S2 = B_.S[1 - cur_].template as<TB>();
+    TB* HS2 = B_.HS[1 - cur_].template as<TB>();
+    double* M = sm_.M.as<double>();
+    if (p_.fold)
+      launch_gram<TB>(n, HS, B_.ld, mact, HS, B_.ld, mact, M, mact, s_);
+    else
+      launch_gram<TB>(n, S, B_.ld, mact, HS, B_.ld, mact, M, mact, s_);
+    if (p_.sign != 1.0)
+      small_gemm(mact, mact, 0, 0.0, M, mact, false, M, mact, false, p_.sign, M, mact, s_);
+    small_eigh(mact, M, mact, sm_.w.as<double>(), sm_.V.as<double>(), mact, sm_.ew.as<double>(),
+               s_);
+    mu_.resize(b);
+    MBL_HIP(hipMemcpyAsync(mu_.data(), sm_.w.as<double>(), b * sizeof(double),
+                           hipMemcpyDeviceToHost, s_));
+    // C = V[:, 0:b] (mact x b, ld b)
+    double* C = sm_.C.as<double>();
+    MBL_HIP(hipMemcpy2DAsync(C, b * sizeof(double), sm_.V.as<double>(), mact * sizeof(double),
+                             b * sizeof(double), mact, hipMemcpyDeviceToDevice, s_));
+    // X' = S C, HX' = HS C
+    launch_combine<TB>(n, S, B_.ld, mact, C, b, S2, B_.ld, b, 0.0, s_);
+    launch_combine<TB>(n, HS, B_.ld, mact, C, b, HS2, B_.ld, b, 0.0, s_);
+    int bp_new = 0;
+    if (mact > b) {
+      // C^ = C with the X rows zeroed, projected off C twice, orthonormalised.
+      double* Ch = sm_.Ch.as<double>();
+      MBL_HIP(hipMemcpyAsync(Ch, C, (size_t)mact * b * sizeof(double), hipMemcpyDeviceToDevice,
+                             s_));
+      MBL_HIP(hipMemsetAsync(Ch, 0, (size_t)b * b * sizeof(double), s_));
+      double* T1 = sm_.T1.as<double>();
+      for (int pass = 0; pass < 2; ++pass) {
+        small_gemm(b, b, mact, 1.0, C, b, true, Ch, b, false, 0.0, T1, b, s_);   // C^T C^
+        small_gemm(mact, b, b, -1.0, C, b, false, T1, b, false, 1.0, Ch, b, s_);  // C^ -= C T1
+      }
+      small_gemm(b, b, mact, 1.0, Ch, b, true, Ch, b, false, 0.0, T1, b, s_);
+      const int k = chol_drop(b, T1, b, 1e-14, sm_.Rinv.as<double>(), sm_.cw.as<double>(),
+                              sm_.cnt.as<int>(), s_);
+      double* T2 = sm_.T2.as<double>();
+      small_gemm(mact, k, b, 1.0, Ch, b, false, sm_.Rinv.as<double>(), b, false, 0.0, T2, b, s_);
+      launch_combine<TB>(n, S, B_.ld, mact, T2, b, S2 + b, B_.ld, k, 0.0, s_);
+      launch_combine<TB>(n, HS, B_.ld, mact, T2, b, HS2 + b, B_.ld, k, 0.0, s_);
+      bp_new = k;
+    }
+    cur_ = 1 - cur_;
+    bp_ = bp_new;
+    MBL_HIP(hipStreamSynchronize(s_));
+    st_.t_rr += secs(t0);
+  }
+
+  // H-Rayleigh-Ritz inside span(X): wanted Ritz values (of H - sigma, or of
+  // sign*H in plain mode) and residual norms.  Leaves Zsel (b x nev) in sm_.Zs.
+  void check(std::vector<double>& theta, std::vector<double>& res) {
+    const int b = p_.b, nev = p_.nev;
+    const int64_t n = H_.n;
+    const auto t0 = clk::now();
+    TB* X = B_.S[cur_].template as<TB>();
+    TB* HX = B_.HS[cur_].template as<TB>();
+    double* K = sm_.K.as<double>();
+    launch_gram<TB>(n, X, B_.ld, b, HX, B_.ld, b, K, b, s_);
+    if (p_.sign != 1.0) small_gemm(b, b, 0, 0.0, K, b, false, K, b, false, p_.sign, K, b, s_);
+    small_eigh(b, K, b, sm_.th.as<double>(), sm_.Z.as<double>(), b, sm_.ew.as<double>(), s_);
+    if (p_.fold) {
+      select_nearest(b, nev, sm_.th.as<double>(), sm_.sel.as<int>(), s_);
+    } else {
+      std::vector<int> sel(nev);
+      for (int j = 0; j < nev; ++j) sel[j] = j;
+      MBL_HIP(hipMemcpyAsync(sm_.sel.get(), sel.data(), nev * sizeof(int), hipMemcpyHostToDevice,
+                             s_));
+    }
+    gather_cols(b, nev, sm_.sel.as<int>(), sm_.Z.as<double>(), b, sm_.Zs.as<double>(), nev, s_);
+    std::vector<double> th_all(b);
+    std::vector<int> sel(nev);
+    MBL_HIP(hipMemcpyAsync(th_all.data(), sm_.th.as<double>(), b * sizeof(double),
+                           hipMemcpyDeviceToHost, s_));
+    MBL_HIP(hipMemcpyAsync(sel.data(), sm_.sel.as<int>(), nev * sizeof(int), hipMemcpyDeviceToHost,
+                           s_));
+    MBL_HIP(hipStreamSynchronize(s_));
+    theta.resize(nev);
+    for (int j = 0; j < nev; ++j) theta[j] = th_all[sel[j]];
+    // residual block: sign*HX Zs - X Zs diag(theta)
+    double* Zt = sm_.T1.as<double>();
+    MBL_HIP(hipMemcpyAsync(Zt, sm_.Zs.as<double>(), (size_t)b * nev * sizeof(double),
+                           hipMemcpyDeviceToDevice, s_));
+    {
+      std::vector<double> D((size_t)nev * nev, 0.0);
+      for (int j = 0; j < nev; ++j) D[(size_t)j * nev + j] = -theta[j];
+      MBL_HIP(hipMemcpyAsync(sm_.T2.get(), D.data(), D.size() * sizeof(double),
+                             hipMemcpyHostToDevice, s_));
+      small_gemm(b, nev, nev, 1.0, sm_.Zs.as<double>(), nev, false, sm_.T2.as<double>(), nev,
+                 false, 0.0, Zt, nev, s_);
+    }
+    TB* Rr = B_.tmp.template as<TB>();
+    if (p_.sign != 1.0) {
+      double* Zsg = sm_.Ch.as<double>();
+      MBL_HIP(hipMemcpyAsync(Zsg, sm_.Zs.as<double>(), (size_t)b * nev * sizeof(double),
+                             hipMemcpyDeviceToDevice, s_));
+      small_gemm(b, nev, 0, 0.0, Zsg, nev, false, Zsg, nev, false, p_.sign, Zsg, nev, s_);
+      launch_combine<TB>(n, HX, B_.ld, b, Zsg, nev, Rr, b, nev, 0.0, s_);
+    } else {
+      launch_combine<TB>(n, HX, B_.ld, b, sm_.Zs.as<double>(), nev, Rr, b, nev, 0.0, s_);
+    }
+    launch_combine<TB>(n, X, B_.ld, b, Zt, nev, Rr, b, nev, 1.0, s_);
+    launch_gram<TB>(n, Rr, b, nev, Rr, b, nev, sm_.K.as<double>(), nev, s_);
+    std::vector<double> G((size_t)nev * nev);
+    MBL_HIP(hipMemcpyAsync(G.data(), sm_.K.as<double>(), G.size() * sizeof(double),
+                           hipMemcpyDeviceToHost, s_));
+    MBL_HIP(hipStreamSynchronize(s_));
+    res.resize(nev);
+    for (int j = 0; j < nev; ++j) res[j] = std::sqrt(std::max(0.0, G[(size_t)j * nev + j]));
+    st_.t_rr += secs(t0);
+  }
+
+  // One LOBPCG step: W from the residual, then RR on [X P W].
+  // Returns false when no new direction survived (stagnation).
+  template <class TP>
+  bool step(const TP* jac, int m) {
+    const int b = p_.b;
+    const int64_t n = H_.n;
+    TB* S = B_.S[cur_].template as<TB>();
+    TB* HS = B_.HS[cur_].template as<TB>();
+    TB* R = B_.R.template as<TB>();
+    // A-residual R = sign*(op) applied to HX minus X diag(mu)
+    {
+      const auto t0 = clk::now();
+      std::vector<double> D((size_t)b * b, 0.0);
+      for (int j = 0; j < b; ++j) D[(size_t)j * b + j] = -mu_[j];
+      MBL_HIP(hipMemcpyAsync(sm_.T2.get(), D.data(), D.size() * sizeof(double),
+                             hipMemcpyHostToDevice, s_));
+      if (p_.fold) {
+        apply(HS, B_.ld, R, b, b);
+      } else {
+        // R = sign * HX
+        std::vector<double> I((size_t)b * b, 0.0);
+        for (int j = 0; j < b; ++j) I[(size_t)j * b + j] = p_.sign;
+        MBL_HIP(hipMemcpyAsync(sm_.T1.get(), I.data(), I.size() * sizeof(double),
+                               hipMemcpyHostToDevice, s_));
+        launch_combine<TB>(n, HS, B_.ld, b, sm_.T1.as<double>(), b, R, b, b, 0.0, s_);
+      }
+      launch_combine<TB>(n, S, B_.ld, b, sm_.T2.as<double>(), b, R, b, b, 1.0, s_);
+      MBL_HIP(hipStreamSynchronize(s_));
+      st_.t_rr += secs(t0);
+    }
+    TB* W = S + b + bp_;
+    const int64_t ld = B_.ld;
+    if (p_.fold && m > 0) {
+      const auto t0 = clk::now();
+      if constexpr (std::is_same<TB, TP>::value) {
+        run_pcg<TP>(H_, p_.sigma, jac, R, b, W, ld, b, m, s_);
+      } else {
+        DevBuf rp((size_t)n * b * sizeof(TP), s_), wp((size_t)n * b * sizeof(TP), s_);
+        launch_convert<TB, TP>(n, b, R, b, rp.as<TP>(), b, s_);
+        run_pcg<TP>(H_, p_.sigma, jac, rp.as<TP>(), b, wp.as<TP>(), b, b, m, s_);
+        launch_convert<TP, TB>(n, b, wp.as<TP>(), b, W, ld, s_);
+        MBL_HIP(hipStreamSynchronize(s_));
+      }
+      st_.applies += 2LL * m;
+      st_.pcg_steps += m;
+      st_.t_pcg += secs(t0);
+    } else {
+      copy_cols<TB>(n, b, R, b, W, ld, s_);
+    }
+    const auto t0 = clk::now();
+    // orthogonalise W against [X P] twice, then Cholesky-QR twice
+    const int xp = b + bp_;
+    for (int pass = 0; pass < 2; ++pass) {
+      launch_gram<TB>(n, S, ld, xp, W, ld, b, sm_.T1.as<double>(), b, s_);
+      small_gemm(xp, b, 0, 0.0, sm_.T1.as<double>(), b, false, sm_.T1.as<double>(), b, false,
+                 -1.0, sm_.T1.as<double>(), b, s_);  // negate
+      launch_combine<TB>(n, S, ld, xp, sm_.T1.as<double>(), b, W, ld, b, 1.0, s_);
+    }
+    const int bw = cholqr2(W, ld, b);
+    st_.t_rr += secs(t0);
+    if (bw == 0) return false;
+    apply(W, ld, HS + b + bp_, ld, bw);
+    rr(b + bp_ + bw);
+    return true;
+  }
+
+  // Eigen-vectors of the wanted pairs: V = X Zsel (n x nev) in FP64.
+  void vectors(double* V, int64_t ldv) {
+    const int b = p_.b, nev = p_.nev;
+    TB* X = B_.S[cur_].template as<TB>();
+    if constexpr (std::is_same<TB, double>::value) {
+      launch_combine<double>(H_.n, X, B_.ld, b, sm_.Zs.as<double>(), nev, V, ldv, nev, 0.0, s_);
+    } else {
+      DevBuf t((size_t)H_.n * nev * sizeof(TB), s_);
+      launch_combine<TB>(H_.n, X, B_.ld, b, sm_.Zs.as<double>(), nev, t.as<TB>(), nev, nev, 0.0,
+                         s_);
+      launch_convert<TB, double>(H_.n, nev, t.as<TB>(), nev, V, ldv, s_);
+      MBL_HIP(hipStreamSynchronize(s_));
+    }
+  }
+
+  TB* X() { return B_.S[cur_].template as<TB>(); }
+  int64_t ldx() const { return B_.ld; }
+  const std::vector<double>& mu() const { return mu_; }
+
+ private:
+  const Ham& H_;
+  const Params& p_;
+  Small& sm_;
+  Stats& st_;
+  hipStream_t s_;
+  PhaseBufs<TB> B_;
+  int cur_ = 0;
+  int bp_ = 0;
+  std::vector<double> mu_;
+};
+
+// Fresh FP64 residuals of V (n x nev) with values theta (of H - sigma).
+std::vector<double> fresh_residuals(const Ham& H, double sigma, const double* V, int64_t ldv,
+                                    int nev, const std::vector<double>& theta, Stats& st,
+                                    hipStream_t s) {
+  const int64_t n = H.n;
+  DevBuf HV((size_t)n * nev * sizeof(double), s), D((size_t)nev * nev * sizeof(double), s),
+      G((size_t)nev * nev * sizeof(double), s);
+  launch_apply<double>(H, sigma, V, ldv, HV.as<double>(), nev, nev, s);
+  st.applies += 1;
+  std::vector<double> d((size_t)nev * nev, 0.0);
+  for (int j = 0; j < nev; ++j) d[(size_t)j * nev + j] = -theta[j];
+  MBL_HIP(hipMemcpyAsync(D.get(), d.data(), d.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  launch_combine<double>(n, V, ldv, nev, D.as<double>(), nev, HV.as<double>(), nev, nev, 1.0, s);
+  launch_gram<double>(n, HV.as<double>(), nev, nev, HV.as<double>(), nev, nev, G.as<double>(), nev,
+                      s);
+  std::vector<double> g((size_t)nev * nev);
+  MBL_HIP(hipMemcpyAsync(g.data(), G.get(), g.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  MBL_HIP(hipStreamSynchronize(s));
+  std::vector<double> r(nev);
+  for (int j = 0; j < nev; ++j) r[j] = std::sqrt(std::max(0.0, g[(size_t)j * nev + j]));
+  return r;
+}
+
+double maxv(const std::vector<double>& v) {
+  double m = 0;
+  for (double x : v) m = std::max(m, x);
+  return m;
+}
+
+// Runs LOBPCG iterations of one phase until the wanted residuals are below
+// stop_tol, stagnation (no 10% progress in `patience` steps, if patience > 0)
+// or the iteration budget is used.  Returns true on reaching stop_tol.
+template <class TB, class TP>
+bool run_phase(Phase<TB>& ph, const TP* jac, const Params& p, double stop_tol, int patience,
+               int& iters_left, Stats& st, std::vector<double>& theta, std::vector<double>& res,
+               const char* tag) {
+  const int m = p.pcg_iters;
+  double best = INFINITY;
+  int since = 0;
+  while (true) {
+    ph.check(theta, res);
+    const double r = maxv(res);
+    if (p.verbose)
+      std::fprintf(stderr, "[mbl %s] iter %d applies %lld max_resid %.3e\n", tag, st.iters,
+                   (long long)st.applies, r);
+    if (r <= stop_tol) return true;
+    if (patience > 0) {
+      if (r < 0.9 * best) {
+        best = r;
+        since = 0;
+      } else if (++since >= patience) {
+        return false;
+      }
+    }
+    if (iters_left <= 0) return false;
+    --iters_left;
+    ++st.iters;
+    if (!ph.step(jac, m)) return false;
+  }
+}
+
+}  // namespace
+
+// Interior solve.  evals/resid host (nev), evecs device (may be null).
+mbl_status solve_interior(const Ham& H, double sigma, int nev, int b, double tol,
+                          const mbl_solve_opts& o, double* evals, double* evecs, int64_t ldv,
+                          double* resid, mbl_solve_info* info, hipStream_t s) {
+  const auto t_start = clk::now();
+  Params p;
+  p.sigma = sigma;
+  p.nev = nev;
+  p.b = b;
+  p.tol = tol;
+  p.max_iter = o.max_iter > 0 ? o.max_iter : 400;
+  p.pcg_iters = o.pcg_iters > 0 ? o.pcg_iters : default_pcg_iters(H.n);
+  p.verbose = o.verbose;
+  p.seed = o.seed;
+  Stats st;
+  Small sm(b, s);
+  const int64_t n = H.n;
+  const int prec = o.precision;
+  std::vector<double> theta, res;
+  int iters_left = p.max_iter;
+  DevBuf V((size_t)n * nev * sizeof(double), s);
+  DevBuf jac32, jac64;
+  bool ok = false;
+
+  DevBuf X0((size_t)n * b * sizeof(double), s);
+  launch_randn<double>(n, b, p.seed, X0.as<double>(), b, s);
+  if (prec == MBL_MIXED || prec == MBL_PCG32) {
+    jac32.reset((size_t)n * sizeof(float), s);
+    launch_jacobi<float>(H, sigma, jac32.as<float>(), s);
+  }
+  if (prec == MBL_F64) {
+    jac64.reset((size_t)n * sizeof(double), s);
+    launch_jacobi<double>(H, sigma, jac64.as<double>(), s);
+  }
+  if (prec == MBL_MIXED) {
+    // phase 1: FP32 blocks until the FP32 floor
+    Phase<float> ph(H, p, sm, st, s);
+    {
+      DevBuf x32((size_t)n * b * sizeof(float), s);
+      launch_convert<double, float>(n, b, X0.as<double>(), b, x32.as<float>(), b, s);
+      ph.init(x32.as<float>(), b);
+    }
+    const double sw = std::max(tol, 1e-5);
+    run_phase<float, float>(ph, jac32.as<float>(), p, sw, 4, iters_left, st, theta, res, "fp32");
+    launch_convert<float, double>(n, b, ph.X(), ph.ldx(), X0.as<double>(), b, s);
+    MBL_HIP(hipStreamSynchronize(s));
+  }
+  {
+    Phase<double> ph(H, p, sm, st, s);
+    ph.init(X0.as<double>(), b);
+    X0.release();
+    const int it0 = st.iters;
+    while (true) {
+      bool reached;
+      if (prec == MBL_F64)
+        reached = run_phase<double, double>(ph, jac64.as<double>(), p, tol, 0, iters_left, st,
+                                            theta, res, "fp64");
+      else
+        reached = run_phase<double, float>(ph, jac32.as<float>(), p, tol, 0, iters_left, st, theta,
+                                           res, "fp64/pcg32");
+      ph.vectors(V.as<double>(), nev);
+      res = fresh_residuals(H, sigma, V.as<double>(), nev, nev, theta, st, s);
+      ok = reached && maxv(res) <= tol;
+      if (ok || !reached || iters_left <= 0) break;
+      // tracked residuals passed but fresh ones did not: one more step
+      --iters_left;
+      ++st.iters;
+      bool stepped;
+      if (prec == MBL_F64)
+        stepped = ph.step(jac64.as<double>(), p.pcg_iters);
+      else
+        stepped = ph.step(jac32.as<float>(), p.pcg_iters);
+      if (!stepped) break;
+    }
+    st.iters_fp64 = (prec == MBL_MIXED) ? st.iters - it0 : st.iters;
+  }
+  // outputs, ascending theta already
+  for (int j = 0; j < nev; ++j) {
+    evals[j] = theta[j] + sigma;
+    if (resid) resid[j] = res[j];
+  }
+  if (evecs)
+    MBL_HIP(hipMemcpy2DAsync(evecs, ldv * sizeof(double), V.get(), nev * sizeof(double),
+                             nev * sizeof(double), n, hipMemcpyDeviceToDevice, s));
+  MBL_HIP(hipStreamSynchronize(s));
+  if (info) {
+    info->iters = st.iters;
+    info->iters_fp64 = st.iters_fp64;
+    info->applies = st.applies;
+    info->pcg_steps = st.pcg_steps;
+    info->t_pcg = st.t_pcg;
+    info->t_rr = st.t_rr;
+    info->max_resid = maxv(res);
+    int nc = 0;
+    for (double r : res) nc += (r <= tol);
+    info->nconv = nc;
+    info->seconds = secs(t_start);
+  }
+  return ok ? MBL_OK : MBL_ENOCONV;
+}
+
+// Extreme eigenvalues by plain LOBPCG on +H and -H (block 4, no preconditioner).
+mbl_status spectrum_bounds(const Ham& H, double tol, double* emin, double* emax, hipStream_t s) {
+  const int64_t n = H.n;
+  const int b = (int)std::min<int64_t>(4, n / 2 > 0 ? n / 2 : 1);
+  if (n <= 2) {
+    // tiny sectors: Rayleigh-Ritz on the identity basis is exact
+    Params p;
+    p.fold = false;
+    p.b = (int)n;
+    p.nev = (int)n;
+    Stats st;
+    Small sm((int)n, s);
+    DevBuf I((size_t)n * n * sizeof(double), s);
+    std::vector<double> e((size_t)n * n, 0.0);
+    for (int64_t i = 0; i < n; ++i) e[(size_t)i * n + i] = 1.0;
+    MBL_HIP(hipMemcpyAsync(I.get(), e.data(), e.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    DevBuf HI((size_t)n * n * sizeof(double), s);
+    launch_apply<double>(H, 0.0, I.as<double>(), n, HI.as<double>(), n, (int)n, s);
+    std::vector<double> hm((size_t)n * n);
+    MBL_HIP(hipMemcpyAsync(hm.data(), HI.get(), hm.size() * sizeof(double), hipMemcpyDeviceToHost,
+                           s));
+    MBL_HIP(hipStreamSynchronize(s));
+    if (n == 1) {
+      *emin = *emax = hm[0];
+    } else {
+      const double a = hm[0], d = hm[3], c = hm[1];
+      const double mid = 0.5 * (a + d), rad = std::sqrt(0.25 * (a - d) * (a - d) + c * c);
+      *emin = mid - rad;
+      *emax = mid + rad;
+    }
+    return MBL_OK;
+  }
+  double out[2];
+  for (int k = 0; k < 2; ++k) {
+    Params p;
+    p.fold = false;
+    p.sign = k == 0 ? 1.0 : -1.0;
+    p.b = b;
+    p.nev = 1;
+    p.seed = 12345 + k;
+    Stats st;
+    Small sm(b, s);
+    Phase<double> ph(H, p, sm, st, s);
+    DevBuf X0((size_t)n * b * sizeof(double), s);
+    launch_randn<double>(n, b, p.seed, X0.as<double>(), b, s);
+    ph.init(X0.as<double>(), b);
+    std::vector<double> theta, res;
+    int left = 5000;
+    // residual r bounds the eigenvalue error by r^2 / gap for an extreme pair
+    const double rtol = std::max(1e-9, std::sqrt(tol) * 1e-2);
+    run_phase<double, double>(ph, (const double*)nullptr, p, rtol, 0, left, st, theta, res,
+                              "bounds");
+    out[k] = p.sign * theta[0];
+  }
+  *emin = out[0];
+  *emax = out[1];
+  return MBL_OK;
+}
+
+}  // namespace mbl
