@@ -163,6 +163,9 @@ typedef struct {
   int pcg_iters;         /* CG steps per LOBPCG iteration; 0 = by dimension  */
   int precision;         /* mbl_precision: MBL_F64, MBL_MIXED or MBL_PCG32   */
   int verbose;           /* 1: one line per outer iteration on stderr        */
+  int timing;            /* 1: time the two fused CG apply kernels with HIP
+                            events on the solve's stream (first 64 CG steps
+                            of every inner solve)                            */
   uint64_t seed;         /* starting block (device counter-based generator)  */
 } mbl_solve_opts;
 
@@ -176,6 +179,11 @@ typedef struct {
   double t_pcg;          /* seconds in the PCG inner solves                  */
   double t_rr;           /* seconds in Gram / Rayleigh-Ritz / orthonormalising */
   double max_resid;      /* max ||H x - lambda x||_2 over the returned pairs */
+  /* opts.timing: timed launches and their summed milliseconds of the CG
+     kernels T = (H - sigma) p (+ |T|^2) and q = (H - sigma) T (+ x, r update,
+     r.z); FP32 and FP64 inner solves are counted separately.               */
+  int64_t cg_apply1_launches[2], cg_apply2_launches[2];  /* [0]=FP64 [1]=FP32 */
+  double cg_apply1_ms[2], cg_apply2_ms[2];
 } mbl_solve_info;
 
 mbl_status mbl_solve_opts_default(mbl_solve_opts* opts);

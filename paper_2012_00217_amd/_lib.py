@@ -8,7 +8,7 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libmbl.so")
+LIB_PATH = os.environ.get("MBL_LIBRARY") or os.path.join(HERE, "libmbl.so")
 
 MBL_OK, MBL_EINVAL, MBL_ENOMEM, MBL_EDEVICE, MBL_ENOCONV, MBL_EBREAKDOWN, MBL_EINTERNAL = (
     0, -1, -2, -3, -4, -5, -8)
@@ -20,13 +20,15 @@ STATUS_NAMES = {0: "MBL_OK", -1: "MBL_EINVAL", -2: "MBL_ENOMEM", -3: "MBL_EDEVIC
 
 class SolveOpts(C.Structure):
     _fields_ = [("max_iter", C.c_int), ("pcg_iters", C.c_int), ("precision", C.c_int),
-                ("verbose", C.c_int), ("seed", C.c_uint64)]
+                ("verbose", C.c_int), ("timing", C.c_int), ("seed", C.c_uint64)]
 
 
 class SolveInfo(C.Structure):
     _fields_ = [("iters", C.c_int), ("iters_fp64", C.c_int), ("nconv", C.c_int),
                 ("applies", C.c_int64), ("pcg_steps", C.c_int64), ("seconds", C.c_double),
-                ("t_pcg", C.c_double), ("t_rr", C.c_double), ("max_resid", C.c_double)]
+                ("t_pcg", C.c_double), ("t_rr", C.c_double), ("max_resid", C.c_double),
+                ("cg_apply1_launches", C.c_int64 * 2), ("cg_apply2_launches", C.c_int64 * 2),
+                ("cg_apply1_ms", C.c_double * 2), ("cg_apply2_ms", C.c_double * 2)]
 
 
 vp, i64, dbl, cint = C.c_void_p, C.c_int64, C.c_double, C.c_int

@@ -131,7 +131,7 @@ class Hamiltonian:
 
     def solve(self, sigma, nev, block, tol=1e-10, precision="f64", max_iter=400, pcg_iters=0,
               seed=0x5EED, verbose=False, want_vectors=True, device="cuda", stream=None,
-              raise_on_noconv=True):
+              raise_on_noconv=True, timing=False):
         """nev eigenpairs nearest sigma by LOBPCG on the spectral fold.
 
         Returns (evals [nev] numpy, evecs (n, nev) float64 tensor or None,
@@ -144,6 +144,7 @@ class Hamiltonian:
         opts.pcg_iters = int(pcg_iters)
         opts.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         opts.verbose = int(bool(verbose))
+        opts.timing = int(bool(timing))
         opts.seed = int(seed)
         ev = np.zeros(nev)
         rs = np.zeros(nev)
@@ -154,7 +155,10 @@ class Hamiltonian:
             ev.ctypes.data_as(_lib.dptr), C.c_void_p(V.data_ptr()) if V is not None else None,
             nev, rs.ctypes.data_as(_lib.dptr), C.byref(info), _stream(stream))
         _lib.check(st, allow=() if raise_on_noconv else (_lib.MBL_ENOCONV,))
-        d = {f: getattr(info, f) for f, _ in _lib.SolveInfo._fields_}
+        d = {}
+        for f, _ in _lib.SolveInfo._fields_:
+            v = getattr(info, f)
+            d[f] = list(v) if hasattr(v, "__len__") else v
         d["status"] = _lib.STATUS_NAMES.get(st, st)
         return ev, V, rs, d
 

@@ -35,6 +35,48 @@ struct alignas(sizeof(T) * VE) Pack {
   T v[VE];
 };
 
+#ifndef MBL_APPLY_NT_STORE
+#define MBL_APPLY_NT_STORE 1
+#endif
+
+// Streaming store of one vector: outputs are not re-read by the same kernel,
+// so they should not displace gathered rows of X from the L2.
+template <class T, int VE>
+__device__ inline void store_stream(T* p, const Pack<T, VE>& v) {
+#if MBL_APPLY_NT_STORE
+  if constexpr (VE == 1) {
+    __builtin_nontemporal_store(v.v[0], p);
+  } else {
+    typedef T vec_t __attribute__((ext_vector_type(VE)));
+    vec_t x;
+#pragma unroll
+    for (int e = 0; e < VE; ++e) x[e] = v.v[e];
+    __builtin_nontemporal_store(x, reinterpret_cast<vec_t*>(p));
+  }
+#else
+  *reinterpret_cast<Pack<T, VE>*>(p) = v;
+#endif
+}
+
+// Tile schedule.  Tiles are dealt to the 8 XCDs in groups: group g covers
+// tiles [g*8*grp, (g+1)*8*grp) and XCD x takes the grp consecutive tiles
+// starting at g*8*grp + x*grp.  grp = ceil(ntiles/8) gives each XCD one
+// contiguous eighth of the rows; grp = 1 interleaves single tiles; values in
+// between keep a compact sweep front (good for the shared MALL) while each
+// XCD still sees runs of consecutive rows (good for its own L2).  Workgroup k
+// runs on XCD k % 8; the workgroups of one XCD walk its tiles in order.
+struct TileSched {
+  int64_t ntiles;
+  int grp;
+};
+
+__device__ inline int64_t sched_tile(const TileSched& t, int64_t u, int x, bool* done) {
+  const int64_t g = u / t.grp;
+  const int64_t base = g * 8 * t.grp;
+  *done = base >= t.ntiles;
+  return base + (int64_t)x * t.grp + (u - g * t.grp);
+}
+
 enum { EPI_PLAIN = 0, EPI_NORM2 = 1, EPI_PCG = 2 };
 
 template <class T>
@@ -60,11 +102,12 @@ struct ApplyArgs {
   double sigma, halfJ;
   int L;
   int col0, w, log2G;
-  int64_t ntiles, tiles_per_xcd;
+  TileSched ts;
 };
 
 constexpr int kWaves = 4;
 constexpr int kThreads = 64 * kWaves;
+
 
 template <class T, int VE, int NV>
 __device__ inline void block_reduce_store(double (&red)[NV * VE], int log2G, int w,
@@ -90,13 +133,26 @@ __device__ inline void block_reduce_store(double (&red)[NV * VE], int log2G, int
   }
 }
 
+#ifndef MBL_APPLY_BB_BYTES
+#define MBL_APPLY_BB_BYTES 256
+#endif
+
+constexpr int kNoFlip = -2147483647 - 1;  // offset-table entry of an inactive bond
+
+// One wavefront owns RW = 64/G consecutive rows per tile.  Phase A fills the
+// wave's LDS table off[r][i] (r < RW, i < 32) with the row offset of the flip
+// target of bond i in row r, or kNoFlip: the RW*32 entries are spread over all
+// 64 lanes, so each flip target is computed exactly once.  Phase B: the G
+// lanes of a row read four offsets at a time (one LDS load) and gather the
+// target rows' column chunks.
 template <class T, int VE, int NV, int EPI>
 __global__ __launch_bounds__(kThreads) void k_apply(ApplyArgs<T> a) {
   using P = Pack<T, VE>;
-  constexpr int BB = (NV * VE * sizeof(T) >= 32) ? 4 : 8;  // bonds per batch of loads
+  constexpr int BB0 = MBL_APPLY_BB_BYTES / (NV * VE * (int)sizeof(T));
+  constexpr int BB = BB0 <= 1 ? 1 : (BB0 >= 4 ? 4 : 2);  // bonds per batch of loads
   __shared__ uint32_t C[kPascal * kPascal];
+  extern __shared__ double sdyn[];  // [kWaves][w] doubles for reductions, then offset tables
   for (int i = threadIdx.x; i < kPascal * kPascal; i += kThreads) C[i] = a.pascal[i];
-  __syncthreads();
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int G = 1 << a.log2G;
@@ -106,6 +162,9 @@ __global__ __launch_bounds__(kThreads) void k_apply(ApplyArgs<T> a) {
   const int nb = a.L - 1;
   const uint32_t bondmask = nb > 0 ? ((1u << nb) - 1u) : 0u;
   const int cbase = a.col0 + cl * VE;  // first column of unit 0 of this lane
+  const int red_doubles = (EPI == EPI_PLAIN) ? 0 : kWaves * a.w;
+  int* offtab = reinterpret_cast<int*>(sdyn + red_doubles) + wave * (RW * 32);
+  __syncthreads();
 
   double red[NV * VE];
 #pragma unroll
@@ -120,96 +179,117 @@ __global__ __launch_bounds__(kThreads) void k_apply(ApplyArgs<T> a) {
   const T hj = (T)a.halfJ;
 
   const int xcd = blockIdx.x & 7;
-  const int slot = blockIdx.x >> 3;
   const int nslots = gridDim.x >> 3;
-  const int64_t t_begin = (int64_t)xcd * a.tiles_per_xcd;
-  const int64_t t_end = min(t_begin + a.tiles_per_xcd, a.ntiles);
-  for (int64_t tile = t_begin + slot; tile < t_end; tile += nslots) {
-    const int64_t row = tile * (kWaves * RW) + wave * RW + rsub;
-    if (row >= a.n) continue;
-    const uint32_t s = a.states[row];
-    const uint32_t dw = (s ^ (s >> 1)) & bondmask;
-    P own[NV];
-    {
-      const T* xr = a.X + row * a.ldx + cbase;
-#pragma unroll
-      for (int q = 0; q < NV; ++q) own[q] = *reinterpret_cast<const P*>(xr + q * G * VE);
-    }
-    T nbs[NV * VE];
-#pragma unroll
-    for (int k = 0; k < NV * VE; ++k) nbs[k] = (T)0;
-    for (int i0 = 0; i0 < nb; i0 += BB) {
-      P v[BB][NV];
-      bool act[BB];
-#pragma unroll
-      for (int u = 0; u < BB; ++u) {
-        const int i = i0 + u;
-        act[u] = (i < nb) && ((dw >> i) & 1u);
-        int64_t tgt = row;
-        if (act[u]) {
-          const uint32_t t = __popc(s & ((1u << i) - 1u));
-          const int64_t c = C[i * kPascal + t];
-          tgt = ((s >> i) & 1u) ? row + c : row - c;
-          // the flip identity keeps tgt in [0, n); the guard makes a corrupted
-          // state table drop a term instead of reading out of bounds
-          act[u] = (tgt >= 0) && (tgt < a.n);
-        }
-        if (act[u]) {
-          const T* xp = a.X + tgt * a.ldx + cbase;
-#pragma unroll
-          for (int q = 0; q < NV; ++q) v[u][q] = *reinterpret_cast<const P*>(xp + q * G * VE);
+  for (int64_t u = blockIdx.x >> 3;; u += nslots) {
+    bool done;
+    const int64_t tile = sched_tile(a.ts, u, xcd, &done);
+    if (done) break;
+    if (tile >= a.ts.ntiles) continue;
+    const int64_t row0 = tile * (kWaves * RW) + wave * RW;  // first row of this wave
+
+    // Phase A: flip targets of the wave's RW rows, 32 bond slots per row.
+    for (int it = lane; it < RW * 32; it += 64) {
+      const int r = it >> 5, i = it & 31;
+      const int64_t rr = row0 + r;
+      int o = kNoFlip;
+      if (rr < a.n && i < nb) {
+        const uint32_t sr = a.states[rr];
+        if (((sr ^ (sr >> 1)) >> i) & 1u) {
+          const int c = (int)C[i * kPascal + __popc(sr & ((1u << i) - 1u))];
+          const int d = ((sr >> i) & 1u) ? c : -c;
+          // the flip identity keeps the target in [0, n); the guard makes a
+          // corrupted state table drop a term instead of reading out of bounds
+          if (rr + d >= 0 && rr + d < a.n) o = d;
         }
       }
+      offtab[it] = o;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+    // Phase B: gather for this lane's row.
+    const int64_t row = row0 + rsub;
+    if (row < a.n) {
+      const T* xrow = a.X + row * a.ldx + cbase;
+      P own[NV];
 #pragma unroll
-      for (int u = 0; u < BB; ++u)
-        if (act[u]) {
+      for (int q = 0; q < NV; ++q) own[q] = *reinterpret_cast<const P*>(xrow + q * G * VE);
+      T nbs[NV * VE];
+#pragma unroll
+      for (int k = 0; k < NV * VE; ++k) nbs[k] = (T)0;
+      const int* myoff = offtab + rsub * 32;
+      for (int i0 = 0; i0 < nb; i0 += BB) {
+        int o[BB];
+#pragma unroll
+        for (int v = 0; v < BB; ++v) o[v] = myoff[i0 + v];
+        P v[BB][NV];
+#pragma unroll
+        for (int b2 = 0; b2 < BB; ++b2) {
+          if (o[b2] != kNoFlip) {
+            const T* xp = xrow + (int64_t)o[b2] * a.ldx;
+#pragma unroll
+            for (int q = 0; q < NV; ++q) v[b2][q] = *reinterpret_cast<const P*>(xp + q * G * VE);
+          } else {
+#pragma unroll
+            for (int q = 0; q < NV; ++q)
+#pragma unroll
+              for (int e = 0; e < VE; ++e) v[b2][q].v[e] = (T)0;
+          }
+        }
+#pragma unroll
+        for (int b2 = 0; b2 < BB; ++b2)
 #pragma unroll
           for (int q = 0; q < NV; ++q)
 #pragma unroll
-            for (int e = 0; e < VE; ++e) nbs[q * VE + e] += v[u][q].v[e];
-        }
-    }
-    const T ed = (T)(a.diag[row] - a.sigma);
-    T acc[NV * VE];
+            for (int e = 0; e < VE; ++e) nbs[q * VE + e] += v[b2][q].v[e];
+      }
+      const T ed = (T)(a.diag[row] - a.sigma);
+      T acc[NV * VE];
 #pragma unroll
-    for (int q = 0; q < NV; ++q)
+      for (int q = 0; q < NV; ++q)
 #pragma unroll
-      for (int e = 0; e < VE; ++e) acc[q * VE + e] = ed * own[q].v[e] + hj * nbs[q * VE + e];
+        for (int e = 0; e < VE; ++e) acc[q * VE + e] = ed * own[q].v[e] + hj * nbs[q * VE + e];
 
-    if constexpr (EPI == EPI_PLAIN || EPI == EPI_NORM2) {
-      T* yr = a.Y + row * a.ldy + cbase;
+      if constexpr (EPI == EPI_PLAIN || EPI == EPI_NORM2) {
+        T* yr = a.Y + row * a.ldy + cbase;
 #pragma unroll
-      for (int q = 0; q < NV; ++q) {
-        P o;
+        for (int q = 0; q < NV; ++q) {
+          P o2;
 #pragma unroll
-        for (int e = 0; e < VE; ++e) o.v[e] = acc[q * VE + e];
-        *reinterpret_cast<P*>(yr + q * G * VE) = o;
-      }
-      if constexpr (EPI == EPI_NORM2) {
-#pragma unroll
-        for (int k = 0; k < NV * VE; ++k) red[k] += (double)acc[k] * (double)acc[k];
-      }
-    } else {  // EPI_PCG
-      const T* pr = a.p + row * a.ldp + cbase;
-      T* xr = a.x + row * a.ldxv + cbase;
-      T* rr = a.r + row * a.ldr + cbase;
-      const T dinv = (T)1 / a.jac[row];
-#pragma unroll
-      for (int q = 0; q < NV; ++q) {
-        P pv = *reinterpret_cast<const P*>(pr + q * G * VE);
-        P xv = *reinterpret_cast<const P*>(xr + q * G * VE);
-        P rv = *reinterpret_cast<const P*>(rr + q * G * VE);
-#pragma unroll
-        for (int e = 0; e < VE; ++e) {
-          const T al = alpha[q * VE + e];
-          xv.v[e] = xv.v[e] + al * pv.v[e];
-          rv.v[e] = rv.v[e] - al * acc[q * VE + e];
-          red[q * VE + e] += (double)rv.v[e] * (double)(rv.v[e] * dinv);
+          for (int e = 0; e < VE; ++e) o2.v[e] = acc[q * VE + e];
+          store_stream<T, VE>(yr + q * G * VE, o2);
         }
-        *reinterpret_cast<P*>(xr + q * G * VE) = xv;
-        *reinterpret_cast<P*>(rr + q * G * VE) = rv;
+        if constexpr (EPI == EPI_NORM2) {
+#pragma unroll
+          for (int k = 0; k < NV * VE; ++k) red[k] += (double)acc[k] * (double)acc[k];
+        }
+      } else {  // EPI_PCG
+        const T* pr = a.p + row * a.ldp + cbase;
+        T* xr = a.x + row * a.ldxv + cbase;
+        T* rr = a.r + row * a.ldr + cbase;
+        const T dinv = (T)1 / a.jac[row];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+          P pv = *reinterpret_cast<const P*>(pr + q * G * VE);
+          P xv = *reinterpret_cast<const P*>(xr + q * G * VE);
+          P rv = *reinterpret_cast<const P*>(rr + q * G * VE);
+#pragma unroll
+          for (int e = 0; e < VE; ++e) {
+            const T al = alpha[q * VE + e];
+            xv.v[e] = xv.v[e] + al * pv.v[e];
+            rv.v[e] = rv.v[e] - al * acc[q * VE + e];
+            red[q * VE + e] += (double)rv.v[e] * (double)(rv.v[e] * dinv);
+          }
+          store_stream<T, VE>(xr + q * G * VE, xv);
+          store_stream<T, VE>(rr + q * G * VE, rv);
+        }
       }
     }
+    // the next tile's phase A overwrites this wave's table
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
   if constexpr (EPI != EPI_PLAIN) block_reduce_store<T, VE, NV>(red, a.log2G, a.w, a.part);
 }
@@ -232,7 +312,7 @@ struct EltArgs {
   double* part;
   int64_t n;
   int col0, w, log2G;
-  int64_t ntiles, tiles_per_xcd;
+  TileSched ts;
 };
 
 template <class T, int VE, int NV, int MODE>
@@ -260,11 +340,12 @@ __global__ __launch_bounds__(kThreads) void k_pcg_elt(EltArgs<T> a) {
       }
   }
   const int xcd = blockIdx.x & 7;
-  const int slot = blockIdx.x >> 3;
   const int nslots = gridDim.x >> 3;
-  const int64_t t_begin = (int64_t)xcd * a.tiles_per_xcd;
-  const int64_t t_end = min(t_begin + a.tiles_per_xcd, a.ntiles);
-  for (int64_t tile = t_begin + slot; tile < t_end; tile += nslots) {
+  for (int64_t u = blockIdx.x >> 3;; u += nslots) {
+    bool done;
+    const int64_t tile = sched_tile(a.ts, u, xcd, &done);
+    if (done) break;
+    if (tile >= a.ts.ntiles) continue;
     const int64_t row = tile * (kWaves * RW) + wave * RW + rsub;
     if (row >= a.n) continue;
     const T dinv = (T)1 / a.jac[row];
@@ -352,7 +433,9 @@ std::vector<Chunk> plan_chunks(int b, bool aligned16) {
       VE = 1;
       units = b - c;
     }
-    const int NV = units >= 4 ? 4 : (units >= 2 ? 2 : 1);
+    const int lane_units = std::max(1, env_int("MBL_APPLY_LANE_BYTES", 64) / (int)(VE * sizeof(T)));
+    int NV = 1;
+    while (NV * 2 <= std::min(units, std::min(lane_units, VE > 1 ? 8 : 4))) NV *= 2;
     int G = std::min(64, units / NV);
     G = std::min(G, std::max(1, max_bytes / (int)(NV * VE * sizeof(T))));
     int log2G = 0;
@@ -369,17 +452,19 @@ bool al16(const void* p, int64_t ld, size_t es) {
 }
 
 struct Grid {
-  int64_t ntiles, tiles_per_xcd;
+  TileSched ts;
   unsigned nwg;
 };
 
 Grid make_grid(int64_t n, int log2G) {
   const int64_t rows_per_tile = kWaves * (64 >> log2G);
   Grid g;
-  g.ntiles = (n + rows_per_tile - 1) / rows_per_tile;
-  g.tiles_per_xcd = (g.ntiles + 7) / 8;
+  g.ts.ntiles = (n + rows_per_tile - 1) / rows_per_tile;
+  const int64_t per_xcd = (g.ts.ntiles + 7) / 8;
+  const int grp_knob = env_int("MBL_APPLY_XCD_GROUP", 0);
+  g.ts.grp = (int)std::max<int64_t>(1, grp_knob > 0 ? std::min<int64_t>(grp_knob, per_xcd) : per_xcd);
   const int64_t max_slots = std::min(256, std::max(1, env_int("MBL_APPLY_SLOTS_PER_XCD", 256)));
-  const int64_t slots = std::min<int64_t>(g.tiles_per_xcd, max_slots);
+  const int64_t slots = std::min<int64_t>(per_xcd, max_slots);
   g.nwg = (unsigned)(8 * std::max<int64_t>(1, slots));
   return g;
 }
@@ -391,9 +476,9 @@ void dispatch_apply(const Chunk& ch, const Grid& g, ApplyArgs<T> a, hipStream_t 
   a.col0 = ch.col0;
   a.w = ch.w;
   a.log2G = ch.log2G;
-  a.ntiles = g.ntiles;
-  a.tiles_per_xcd = g.tiles_per_xcd;
-  const size_t shm = (EPI == EPI_PLAIN) ? 0 : (size_t)kWaves * ch.w * sizeof(double);
+  a.ts = g.ts;
+  const size_t shm = ((EPI == EPI_PLAIN) ? 0 : (size_t)kWaves * ch.w * sizeof(double)) +
+                     (size_t)kWaves * (64 >> ch.log2G) * 32 * sizeof(int);
   constexpr int VV = 16 / sizeof(T);
 #define MBL_APPLY_CASE(VE_, NV_)                                                             \
   if (ch.VE == VE_ && ch.NV == NV_) {                                                       \
@@ -401,6 +486,7 @@ void dispatch_apply(const Chunk& ch, const Grid& g, ApplyArgs<T> a, hipStream_t 
     MBL_CHECK_LAUNCH();                                                                     \
     return;                                                                                 \
   }
+  MBL_APPLY_CASE(VV, 8)
   MBL_APPLY_CASE(VV, 4)
   MBL_APPLY_CASE(VV, 2)
   MBL_APPLY_CASE(VV, 1)
@@ -416,8 +502,7 @@ void dispatch_elt(const Chunk& ch, const Grid& g, EltArgs<T> a, hipStream_t s) {
   a.col0 = ch.col0;
   a.w = ch.w;
   a.log2G = ch.log2G;
-  a.ntiles = g.ntiles;
-  a.tiles_per_xcd = g.tiles_per_xcd;
+  a.ts = g.ts;
   const size_t shm = (MODE == ELT_INIT) ? (size_t)kWaves * ch.w * sizeof(double) : 0;
   constexpr int VV = 16 / sizeof(T);
 #define MBL_ELT_CASE(VE_, NV_)                                                                 \
@@ -426,6 +511,7 @@ void dispatch_elt(const Chunk& ch, const Grid& g, EltArgs<T> a, hipStream_t s) {
     MBL_CHECK_LAUNCH();                                                                       \
     return;                                                                                   \
   }
+  MBL_ELT_CASE(VV, 8)
   MBL_ELT_CASE(VV, 4)
   MBL_ELT_CASE(VV, 2)
   MBL_ELT_CASE(VV, 1)
@@ -478,9 +564,20 @@ void launch_apply(const Ham& H, double sigma, const T* X, int64_t ldx, T* Y, int
 //           q = (H-sigma) T ; x += alpha p ; r -= alpha q ; rho' = r.M^-1 r
 //           beta = rho'/rho ; p = M^-1 r + beta p
 // Every coefficient stays on the device; no host synchronisation inside.
+void PcgTiming::init() {
+  if (ready) return;
+  for (auto& e : ev) MBL_HIP(hipEventCreate(&e));
+  ready = true;
+}
+
+PcgTiming::~PcgTiming() {
+  if (!ready) return;
+  for (auto& e : ev) (void)hipEventDestroy(e);
+}
+
 template <class T>
 void run_pcg(const Ham& H, double sigma, const T* jac, const T* R, int64_t ldr, T* W, int64_t ldw,
-             int b, int m, hipStream_t s) {
+             int b, int m, hipStream_t s, PcgTiming* tm) {
   const int64_t n = H.n;
   if (n == 0 || b == 0) return;
   DevBuf rbuf((size_t)n * b * sizeof(T), s), pbuf((size_t)n * b * sizeof(T), s),
@@ -530,12 +627,31 @@ void run_pcg(const Ham& H, double sigma, const T* jac, const T* R, int64_t ldr, 
     a2.jac = jac;
     a2.coef = coef;
     a2.part = part.as<double>();
+    const int ntimed = tm ? std::min(m, PcgTiming::kSample) : 0;
+    if (tm) tm->init();
     for (int it = 0; it < m; ++it) {
+      const bool timed = it < ntimed;
+      if (timed) MBL_HIP(hipEventRecord(tm->ev[4 * it + 0], s));
       dispatch_apply<T, EPI_NORM2>(ch, g, a1, s);
+      if (timed) MBL_HIP(hipEventRecord(tm->ev[4 * it + 1], s));
       finalize<FIN_ALPHA>(ch, g, part.as<double>(), coef, s);
+      if (timed) MBL_HIP(hipEventRecord(tm->ev[4 * it + 2], s));
       dispatch_apply<T, EPI_PCG>(ch, g, a2, s);
+      if (timed) MBL_HIP(hipEventRecord(tm->ev[4 * it + 3], s));
       finalize<FIN_BETA>(ch, g, part.as<double>(), coef, s);
       dispatch_elt<T, ELT_PUPD>(ch, g, e, s);
+    }
+    if (ntimed > 0) {
+      MBL_HIP(hipStreamSynchronize(s));
+      for (int it = 0; it < ntimed; ++it) {
+        float a = 0.f, c = 0.f;
+        MBL_HIP(hipEventElapsedTime(&a, tm->ev[4 * it + 0], tm->ev[4 * it + 1]));
+        MBL_HIP(hipEventElapsedTime(&c, tm->ev[4 * it + 2], tm->ev[4 * it + 3]));
+        tm->ms[0] += a;
+        tm->ms[1] += c;
+      }
+      tm->launches[0] += ntimed;
+      tm->launches[1] += ntimed;
     }
   }
   MBL_HIP(hipStreamSynchronize(s));  // work buffers are freed on return
@@ -546,8 +662,8 @@ template void launch_apply<double>(const Ham&, double, const double*, int64_t, d
 template void launch_apply<float>(const Ham&, double, const float*, int64_t, float*, int64_t, int,
                                   hipStream_t);
 template void run_pcg<double>(const Ham&, double, const double*, const double*, int64_t, double*,
-                              int64_t, int, int, hipStream_t);
+                              int64_t, int, int, hipStream_t, PcgTiming*);
 template void run_pcg<float>(const Ham&, double, const float*, const float*, int64_t, float*,
-                             int64_t, int, int, hipStream_t);
+                             int64_t, int, int, hipStream_t, PcgTiming*);
 
 }  // namespace mbl

@@ -103,10 +103,21 @@ template <class T>
 void launch_apply(const Ham& H, double sigma, const T* X, int64_t ldx, T* Y, int64_t ldy, int w,
                   hipStream_t s);
 
+// Optional HIP-event timing of the two fused CG apply kernels.
+struct PcgTiming {
+  static constexpr int kSample = 64;  // timed CG steps per inner solve
+  hipEvent_t ev[4 * kSample] = {};
+  bool ready = false;
+  int64_t launches[2] = {0, 0};
+  double ms[2] = {0, 0};
+  void init();
+  ~PcgTiming();
+};
+
 // PCG: W = PCG_m(R) (columns independent) with Jacobi diagonal jac.
 template <class T>
 void run_pcg(const Ham& H, double sigma, const T* jac, const T* R, int64_t ldr, T* W, int64_t ldw,
-             int b, int m, hipStream_t s);
+             int b, int m, hipStream_t s, PcgTiming* tm = nullptr);
 
 // Jacobi diagonal of the fold, d = (E - sigma)^2 + (J/2)^2 * (#active bonds).
 template <class T>

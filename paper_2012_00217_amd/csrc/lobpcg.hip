@@ -64,6 +64,8 @@ struct Stats {
   int iters = 0, iters_fp64 = 0;
   int64_t applies = 0, pcg_steps = 0;
   double t_pcg = 0, t_rr = 0;
+  bool timing = false;
+  PcgTiming tm[2];  // [0] FP64 inner solves, [1] FP32 inner solves
 };
 
 // Small FP64 device workspace of one solve (sizes for m = 3b).
@@ -317,12 +319,13 @@ class Phase {
     const int64_t ld = B_.ld;
     if (p_.fold && m > 0) {
       const auto t0 = clk::now();
+      PcgTiming* tm = st_.timing ? &st_.tm[sizeof(TP) == 4 ? 1 : 0] : nullptr;
       if constexpr (std::is_same<TB, TP>::value) {
-        run_pcg<TP>(H_, p_.sigma, jac, R, b, W, ld, b, m, s_);
+        run_pcg<TP>(H_, p_.sigma, jac, R, b, W, ld, b, m, s_, tm);
       } else {
         DevBuf rp((size_t)n * b * sizeof(TP), s_), wp((size_t)n * b * sizeof(TP), s_);
         launch_convert<TB, TP>(n, b, R, b, rp.as<TP>(), b, s_);
-        run_pcg<TP>(H_, p_.sigma, jac, rp.as<TP>(), b, wp.as<TP>(), b, b, m, s_);
+        run_pcg<TP>(H_, p_.sigma, jac, rp.as<TP>(), b, wp.as<TP>(), b, b, m, s_, tm);
         launch_convert<TP, TB>(n, b, wp.as<TP>(), b, W, ld, s_);
         MBL_HIP(hipStreamSynchronize(s_));
       }
@@ -458,6 +461,7 @@ mbl_status solve_interior(const Ham& H, double sigma, int nev, int b, double tol
   p.verbose = o.verbose;
   p.seed = o.seed;
   Stats st;
+  st.timing = o.timing != 0;
   Small sm(b, s);
   const int64_t n = H.n;
   const int prec = o.precision;
@@ -540,6 +544,12 @@ mbl_status solve_interior(const Ham& H, double sigma, int nev, int b, double tol
     for (double r : res) nc += (r <= tol);
     info->nconv = nc;
     info->seconds = secs(t_start);
+    for (int k = 0; k < 2; ++k) {
+      info->cg_apply1_launches[k] = st.tm[k].launches[0];
+      info->cg_apply2_launches[k] = st.tm[k].launches[1];
+      info->cg_apply1_ms[k] = st.tm[k].ms[0];
+      info->cg_apply2_ms[k] = st.tm[k].ms[1];
+    }
   }
   return ok ? MBL_OK : MBL_ENOCONV;
 }
