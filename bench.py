@@ -159,6 +159,15 @@ def main():
     s = 8 if wl["precision"] == "f64" else 4
 
     if args.cg_only:
+        # calibration for HBM byte counters: an elementwise kernel that reads a
+        # 2 GiB buffer and writes another (well beyond the 256 MB last-level
+        # cache): exactly 2 GiB fetched and 2 GiB written per launch
+        src = torch.ones(1 << 29, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.5, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
         for W, H in hams.items():
             R = torch.randn(n, wl["block"], dtype=torch.float64 if s == 8 else torch.float32,
                             device="cuda")

@@ -106,14 +106,18 @@ __global__ __launch_bounds__(256) void k_gram(int64_t n, const T* __restrict__ A
       }
 }
 
+// One wavefront per output element: lane l sums splits l, l+64, ... in order,
+// then a fixed butterfly folds the 64 lane sums.
 __global__ __launch_bounds__(256) void k_gram_fold(const double* __restrict__ part, int splits,
                                                    int p, int q, double* __restrict__ C,
                                                    int64_t ldc) {
-  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int64_t idx = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (idx >= (int64_t)p * q) return;
   double s = 0.0;
-  for (int sp = 0; sp < splits; ++sp) s += part[(int64_t)sp * p * q + idx];
-  C[(idx / q) * ldc + idx % q] = s;
+  for (int sp = lane; sp < splits; sp += 64) s += part[(int64_t)sp * p * q + idx];
+  for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
+  if (lane == 0) C[(idx / q) * ldc + idx % q] = s;
 }
 
 // Y[r, j] = sum_k A[r, k] C[k, j] + beta Y[r, j].  Tile: 64 rows x 64 columns
@@ -224,8 +228,8 @@ void launch_gram(int64_t n, const T* A, int64_t lda, int p, const T* B, int64_t 
   } else {
     MBL_HIP(hipMemsetAsync(part.get(), 0, part.bytes(), s));
   }
-  hipLaunchKernelGGL(k_gram_fold, dim3(g1((int64_t)p * q)), dim3(256), 0, s, part.as<double>(),
-                     (int)splits, p, q, C, ldc);
+  hipLaunchKernelGGL(k_gram_fold, dim3((unsigned)(((int64_t)p * q + 3) / 4)), dim3(256), 0, s,
+                     part.as<double>(), (int)splits, p, q, C, ldc);
   MBL_CHECK_LAUNCH();
   MBL_HIP(hipStreamSynchronize(s));  // `part` is released on return
 }
