@@ -48,17 +48,6 @@ WORKLOADS = {
 }
 
 
-def kernel_bytes(n, b, s):
-    """Algorithmic bytes per launch of the two fused CG apply kernels.
-
-    apply1: T = (H - sigma) p and |T|^2 -- reads p, writes T, reads the state
-            word (4 B) and diagonal (8 B) of every row.
-    apply2: q = (H - sigma) T, x += alpha p, r -= alpha q, r.M^-1 r -- reads T,
-            p, x, r, writes x, r, reads state, diagonal and Jacobi diagonal.
-    """
-    return {"apply1": 2 * n * b * s + 12 * n, "apply2": 6 * n * b * s + (12 + s) * n}
-
-
 def apply_src_hash():
     with open(APPLY_SRC, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
@@ -200,24 +189,33 @@ def main():
     value = pairs / elapsed
     # dominant kernel from the live event timings (summed over the timed solves)
     k = 0 if s == 8 else 1
-    tot = {"apply1": [0, 0.0], "apply2": [0, 0.0]}
+    tot = {"apply1": [0, 0.0, 0.0], "apply2": [0, 0.0, 0.0]}
     steps_cg = 0
     for step in runs:
         for r in step.values():
             i = r["info"]
-            tot["apply1"][0] += i["cg_apply1_launches"][k]
-            tot["apply1"][1] += i["cg_apply1_ms"][k]
-            tot["apply2"][0] += i["cg_apply2_launches"][k]
-            tot["apply2"][1] += i["cg_apply2_ms"][k]
+            for kk in ("apply1", "apply2"):
+                tot[kk][0] += i[f"cg_{kk}_launches"][k]
+                tot[kk][1] += i[f"cg_{kk}_ms"][k]
+                tot[kk][2] += i[f"cg_{kk}_bytes"][k]
             steps_cg += i["pcg_steps"]
     avg = {kk: (v[1] / v[0] if v[0] else float("nan")) for kk, v in tot.items()}
-    dom = max(avg, key=lambda kk: avg[kk] if avg[kk] == avg[kk] else -1)
-    kb = kernel_bytes(n, wl["block"], s)[dom]
+    # Algorithmic bytes per launch over w columns of s-byte scalars (summed by
+    # the library over the timed launches):
+    #   apply1  T = (H - sigma) p, |T|^2: read p, write T, state word and
+    #           diagonal per row                     -> 2 n w s + 12 n
+    #   apply2  q = (H - sigma) T, x += alpha p, r -= alpha q, r.M^-1 r: read
+    #           T, p, x, r, write x, r, state, diagonal, Jacobi diagonal
+    #                                                -> 6 n w s + (12 + s) n
+    # dominant: the larger total time (both kernels run once per CG step)
+    dom = max(tot, key=lambda kk: tot[kk][1])
+    kb = tot[dom][2] / max(1, tot[dom][0])
     achieved = kb / (avg[dom] * 1e-3) / 1e9
     traffic = read_traffic(dom)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
-                "kernel": f"k_apply fused CG {dom} ({'FP64' if s == 8 else 'FP32'}, {wl['block']} columns)",
+                "kernel": f"k_apply fused CG {dom} ({'FP64' if s == 8 else 'FP32'}, "
+                          f"{wl['block']}-column block in cache-sized column chunks)",
                 "algorithmic_bytes_per_launch": kb, "avg_launch_us": round(avg[dom] * 1e3, 2),
                 "timed_launches": tot[dom][0]}
 

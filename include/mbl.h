@@ -51,6 +51,7 @@ typedef enum {
   MBL_EDEVICE = -3,     /* a HIP runtime call failed                          */
   MBL_ENOCONV = -4,     /* solver hit its iteration limit; best pairs returned */
   MBL_EBREAKDOWN = -5,  /* basis collapsed (e.g. starting block rank-deficient) */
+  MBL_ETIMEOUT = -6,    /* mbl_server_wait: request not finished in time      */
   MBL_EINTERNAL = -8    /* unexpected internal failure                        */
 } mbl_status;
 
@@ -184,6 +185,9 @@ typedef struct {
      r.z); FP32 and FP64 inner solves are counted separately.               */
   int64_t cg_apply1_launches[2], cg_apply2_launches[2];  /* [0]=FP64 [1]=FP32 */
   double cg_apply1_ms[2], cg_apply2_ms[2];
+  /* algorithmic bytes of those launches: apply1 2nws + 12n, apply2
+     6nws + (12 + s)n for a launch over w columns of s-byte scalars          */
+  double cg_apply1_bytes[2], cg_apply2_bytes[2];
 } mbl_solve_info;
 
 mbl_status mbl_solve_opts_default(mbl_solve_opts* opts);
@@ -202,6 +206,79 @@ mbl_status mbl_lobpcg_solve(mbl_ham H, double sigma, int nev, int block,
                             double* evals_host, double* evecs_dev, int64_t ldv,
                             double* resid_host, mbl_solve_info* info,
                             hipStream_t stream);
+
+/* ---- many independent solves (paper Sec. 3.1: realisations, disorder
+ * strengths and spectral regions are independent levels of concurrency) ---- */
+
+typedef struct {
+  int L;
+  double Sz, J, Delta;
+  const double* h_host;  /* length L; copied by submit / read during batch   */
+  double sigma;          /* used when eps < 0                                */
+  double eps;            /* >= 0: sigma = Emin + eps (Emax - Emin), with the
+                            bounds computed on the GPU (mbl_spectrum_bounds) */
+  int nev, block;
+  double tol;
+  int precision;         /* MBL_F64, MBL_MIXED or MBL_PCG32                  */
+  int max_iter, pcg_iters;
+  uint64_t seed;
+  int want_vectors;      /* server only: keep the n x nev FP64 eigenvectors on
+                            the device until wait() copies them to
+                            out->evecs_dev (batch: results[i].evecs_dev)     */
+} mbl_problem;
+
+typedef struct {
+  int status;            /* mbl_status of this problem                       */
+  double sigma;          /* shift actually used                              */
+  int nconv, iters;
+  int64_t applies;
+  double max_resid;
+  double seconds;        /* wall time of this problem's solve                */
+  double latency;        /* submit (or batch start) to completion, seconds   */
+  double* evals_host;    /* caller-provided, nev entries (may be NULL)       */
+  double* resid_host;    /* caller-provided, nev entries (may be NULL)       */
+  double* evecs_dev;     /* caller-provided device n x nev, ld ldv (or NULL) */
+  int64_t ldv;
+} mbl_result;
+
+/* Device bytes one solve holds at its peak (n-length blocks of the LOBPCG and
+ * PCG work space plus the sector tables).  Pure host function: this is the
+ * admission model of the server below. */
+mbl_status mbl_footprint_bytes(int L, double Sz, int block, int precision, size_t* bytes);
+
+/* Solve `count` independent problems, `concurrency` at a time (>= 1), each on
+ * its own non-blocking stream of the current device.  Every solve is the same
+ * deterministic computation as mbl_lobpcg_solve, so a problem's result does
+ * not depend on what runs beside it.  Per-problem outcomes are in results[i]
+ * (status, sigma, counts, timings; evals/resid/evecs into caller buffers).
+ * Returns MBL_OK if every problem converged, else the first problem's error. */
+mbl_status mbl_batch_solve(int count, const mbl_problem* problems, mbl_result* results,
+                           int concurrency);
+
+/* Serving loop with continuous batching: submit() queues a request and returns
+ * at once; `concurrency` worker threads take requests in arrival order as soon
+ * as a worker is free and the sum of admitted footprints stays within
+ * hbm_budget (bytes; 0 = 90% of the device's free memory), so requests that
+ * arrive while others run are started beside them.  A request whose footprint
+ * exceeds the whole budget is refused at submit (MBL_ENOMEM).  wait() blocks
+ * for a ticket (timeout_s < 0: forever) and fills `out` (its buffers must stay
+ * valid until wait returns).  Results are kept until waited for.  Thread-safe. */
+typedef struct mbl_server_s* mbl_server;
+typedef struct {
+  int64_t submitted, admitted, completed, rejected, in_flight;
+  double p50_latency, p99_latency;  /* seconds, submit to completion        */
+  double throughput_pairs;          /* converged pairs / s since creation   */
+  size_t budget_bytes, peak_bytes;
+} mbl_server_stats;
+
+mbl_status mbl_server_create(int concurrency, size_t hbm_budget, mbl_server* out);
+mbl_status mbl_server_submit(mbl_server srv, const mbl_problem* request, uint64_t* ticket);
+/* Returns MBL_OK when the request finished (its own status is out->status),
+ * MBL_ETIMEOUT if it is still running after timeout_s. */
+mbl_status mbl_server_wait(mbl_server srv, uint64_t ticket, double timeout_s, mbl_result* out);
+mbl_status mbl_server_stats_get(mbl_server srv, mbl_server_stats* st);
+/* Waits for every submitted request, then stops the workers. */
+mbl_status mbl_server_destroy(mbl_server srv);
 
 #ifdef __cplusplus
 }

@@ -10,12 +10,13 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("MBL_LIBRARY") or os.path.join(HERE, "libmbl.so")
 
-MBL_OK, MBL_EINVAL, MBL_ENOMEM, MBL_EDEVICE, MBL_ENOCONV, MBL_EBREAKDOWN, MBL_EINTERNAL = (
-    0, -1, -2, -3, -4, -5, -8)
+MBL_OK, MBL_EINVAL, MBL_ENOMEM, MBL_EDEVICE, MBL_ENOCONV, MBL_EBREAKDOWN, MBL_ETIMEOUT = (
+    0, -1, -2, -3, -4, -5, -6)
+MBL_EINTERNAL = -8
 MBL_F64, MBL_F32, MBL_MIXED, MBL_PCG32 = 0, 1, 2, 3
 
 STATUS_NAMES = {0: "MBL_OK", -1: "MBL_EINVAL", -2: "MBL_ENOMEM", -3: "MBL_EDEVICE",
-                -4: "MBL_ENOCONV", -5: "MBL_EBREAKDOWN", -8: "MBL_EINTERNAL"}
+                -4: "MBL_ENOCONV", -5: "MBL_EBREAKDOWN", -6: "MBL_ETIMEOUT", -8: "MBL_EINTERNAL"}
 
 
 class SolveOpts(C.Structure):
@@ -28,7 +29,31 @@ class SolveInfo(C.Structure):
                 ("applies", C.c_int64), ("pcg_steps", C.c_int64), ("seconds", C.c_double),
                 ("t_pcg", C.c_double), ("t_rr", C.c_double), ("max_resid", C.c_double),
                 ("cg_apply1_launches", C.c_int64 * 2), ("cg_apply2_launches", C.c_int64 * 2),
-                ("cg_apply1_ms", C.c_double * 2), ("cg_apply2_ms", C.c_double * 2)]
+                ("cg_apply1_ms", C.c_double * 2), ("cg_apply2_ms", C.c_double * 2),
+                ("cg_apply1_bytes", C.c_double * 2), ("cg_apply2_bytes", C.c_double * 2)]
+
+
+class Problem(C.Structure):
+    _fields_ = [("L", C.c_int), ("Sz", C.c_double), ("J", C.c_double), ("Delta", C.c_double),
+                ("h_host", C.POINTER(C.c_double)), ("sigma", C.c_double), ("eps", C.c_double),
+                ("nev", C.c_int), ("block", C.c_int), ("tol", C.c_double),
+                ("precision", C.c_int), ("max_iter", C.c_int), ("pcg_iters", C.c_int),
+                ("seed", C.c_uint64), ("want_vectors", C.c_int)]
+
+
+class Result(C.Structure):
+    _fields_ = [("status", C.c_int), ("sigma", C.c_double), ("nconv", C.c_int),
+                ("iters", C.c_int), ("applies", C.c_int64), ("max_resid", C.c_double),
+                ("seconds", C.c_double), ("latency", C.c_double),
+                ("evals_host", C.POINTER(C.c_double)), ("resid_host", C.POINTER(C.c_double)),
+                ("evecs_dev", C.c_void_p), ("ldv", C.c_int64)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("admitted", C.c_int64), ("completed", C.c_int64),
+                ("rejected", C.c_int64), ("in_flight", C.c_int64), ("p50_latency", C.c_double),
+                ("p99_latency", C.c_double), ("throughput_pairs", C.c_double),
+                ("budget_bytes", C.c_size_t), ("peak_bytes", C.c_size_t)]
 
 
 vp, i64, dbl, cint = C.c_void_p, C.c_int64, C.c_double, C.c_int
@@ -56,6 +81,13 @@ PROTOTYPES = {
     "mbl_solve_opts_default": (cint, [C.POINTER(SolveOpts)]),
     "mbl_lobpcg_solve": (cint, [vp, dbl, cint, cint, dbl, C.POINTER(SolveOpts), dptr, vp, i64,
                                 dptr, C.POINTER(SolveInfo), vp]),
+    "mbl_footprint_bytes": (cint, [cint, dbl, cint, cint, C.POINTER(C.c_size_t)]),
+    "mbl_batch_solve": (cint, [cint, C.POINTER(Problem), C.POINTER(Result), cint]),
+    "mbl_server_create": (cint, [cint, C.c_size_t, C.POINTER(vp)]),
+    "mbl_server_submit": (cint, [vp, C.POINTER(Problem), C.POINTER(C.c_uint64)]),
+    "mbl_server_wait": (cint, [vp, C.c_uint64, dbl, C.POINTER(Result)]),
+    "mbl_server_stats_get": (cint, [vp, C.POINTER(ServerStats)]),
+    "mbl_server_destroy": (cint, [vp]),
 }
 
 _lib = None

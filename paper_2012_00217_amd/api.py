@@ -199,3 +199,134 @@ def small_eigh(A, stream=None):
     _lib.check(_lib.load().mbl_small_eigh(m, C.c_void_p(A.data_ptr()), m, C.c_void_p(w.data_ptr()),
                                           C.c_void_p(V.data_ptr()), m, _stream(stream)))
     return w, V
+
+
+# -- many independent solves -------------------------------------------------
+
+def _problem(d):
+    """ctypes Problem from a dict (keeps the h array alive in the dict)."""
+    h = np.ascontiguousarray(np.asarray(d["h"], dtype=np.float64))
+    d["_h_keep"] = h
+    prec = d.get("precision", "f64")
+    pr = _lib.Problem()
+    pr.L = int(d["L"])
+    pr.Sz = float(d.get("Sz", 0.0))
+    pr.J = float(d.get("J", 1.0))
+    pr.Delta = float(d.get("Delta", 1.0))
+    pr.h_host = h.ctypes.data_as(_lib.dptr)
+    pr.sigma = float(d.get("sigma", 0.0))
+    pr.eps = float(d.get("eps", -1.0))
+    pr.nev = int(d["nev"])
+    pr.block = int(d["block"])
+    pr.tol = float(d.get("tol", 1e-10))
+    pr.precision = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
+    pr.max_iter = int(d.get("max_iter", 400))
+    pr.pcg_iters = int(d.get("pcg_iters", 0))
+    pr.seed = int(d.get("seed", 0x5EED))
+    pr.want_vectors = int(bool(d.get("want_vectors", False)))
+    return pr
+
+
+def _result_dict(r, ev, rs):
+    return {"status": _lib.STATUS_NAMES.get(r.status, r.status), "sigma": r.sigma,
+            "nconv": r.nconv, "iters": r.iters, "applies": r.applies,
+            "max_resid": r.max_resid, "seconds": r.seconds, "latency": r.latency,
+            "evals": ev, "resid": rs}
+
+
+def footprint_bytes(L, block, precision="f64", Sz=0.0):
+    """Device bytes one solve holds at its peak (the server's admission model)."""
+    out = C.c_size_t()
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    _lib.check(_lib.load().mbl_footprint_bytes(int(L), float(Sz), int(block), prec, C.byref(out)))
+    return out.value
+
+
+def batch_solve(problems, concurrency=4, vectors=False, device="cuda"):
+    """Solve a list of problem dicts (keys: L, h, nev, block, and optionally
+    Sz, J, Delta, sigma or eps, tol, precision, max_iter, pcg_iters, seed),
+    `concurrency` at a time.  Returns a list of result dicts (with 'evecs'
+    tensors when vectors=True)."""
+    lib = _lib.load()
+    k = len(problems)
+    P = (_lib.Problem * k)(*[_problem(d) for d in problems])
+    R = (_lib.Result * k)()
+    keep = []
+    for i, d in enumerate(problems):
+        ev = np.zeros(int(d["nev"]))
+        rs = np.zeros(int(d["nev"]))
+        keep.append((ev, rs))
+        R[i].evals_host = ev.ctypes.data_as(_lib.dptr)
+        R[i].resid_host = rs.ctypes.data_as(_lib.dptr)
+        if vectors:
+            from math import comb
+            n = comb(int(d["L"]), int(round(float(d.get("Sz", 0.0)) + d["L"] / 2)))
+            V = torch.empty((n, int(d["nev"])), dtype=torch.float64, device=device)
+            keep[-1] = (ev, rs, V)
+            R[i].evecs_dev = C.c_void_p(V.data_ptr())
+            R[i].ldv = int(d["nev"])
+    lib.mbl_batch_solve(k, P, R, int(concurrency))
+    out = []
+    for i in range(k):
+        dd = _result_dict(R[i], keep[i][0], keep[i][1])
+        if vectors:
+            dd["evecs"] = keep[i][2]
+        out.append(dd)
+    return out
+
+
+class Server:
+    """Serving loop with continuous batching and HBM-footprint admission."""
+
+    def __init__(self, concurrency=4, hbm_budget=0):
+        self._lib = _lib.load()
+        h = C.c_void_p()
+        _lib.check(self._lib.mbl_server_create(int(concurrency), int(hbm_budget), C.byref(h)))
+        self._s = h
+        self._keep = {}
+
+    def submit(self, problem):
+        pr = _problem(dict(problem))
+        t = C.c_uint64()
+        _lib.check(self._lib.mbl_server_submit(self._s, C.byref(pr), C.byref(t)))
+        self._keep[t.value] = problem
+        return t.value
+
+    def wait(self, ticket, timeout=-1.0, vectors_out=None):
+        d = self._keep[ticket]
+        ev = np.zeros(int(d["nev"]))
+        rs = np.zeros(int(d["nev"]))
+        r = _lib.Result()
+        r.evals_host = ev.ctypes.data_as(_lib.dptr)
+        r.resid_host = rs.ctypes.data_as(_lib.dptr)
+        if vectors_out is not None:
+            r.evecs_dev = C.c_void_p(vectors_out.data_ptr())
+            r.ldv = vectors_out.stride(0)
+        st = self._lib.mbl_server_wait(self._s, int(ticket), float(timeout), C.byref(r))
+        if st == _lib.MBL_ETIMEOUT:
+            return None
+        _lib.check(st)
+        del self._keep[ticket]
+        return _result_dict(r, ev, rs)
+
+    def stats(self):
+        st = _lib.ServerStats()
+        _lib.check(self._lib.mbl_server_stats_get(self._s, C.byref(st)))
+        return {f: getattr(st, f) for f, _ in _lib.ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "_s", None) is not None and self._s.value:
+            self._lib.mbl_server_destroy(self._s)
+            self._s = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

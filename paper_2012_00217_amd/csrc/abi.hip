@@ -3,6 +3,7 @@
 // catches everything: no exception crosses the C ABI.
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "common.h"
@@ -47,24 +48,94 @@ bool block_prec(int p) { return p == MBL_F64 || p == MBL_F32; }
 
 }  // namespace
 
-void* dev_alloc(size_t bytes, hipStream_t s) {
+namespace {
+std::mutex g_pool_mu;
+bool g_pool_ready[64] = {};
+
+// Keep freed stream-ordered memory in the device pool instead of returning it
+// to the driver at every synchronisation (once per device).
+void prepare_pool() {
+  int dev = 0;
+  MBL_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return;
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  if (g_pool_ready[dev]) return;
+  hipMemPool_t pool;
+  MBL_HIP(hipDeviceGetDefaultMemPool(&pool, dev));
+  uint64_t keep = UINT64_MAX;
+  MBL_HIP(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep));
+  g_pool_ready[dev] = true;
+}
+}  // namespace
+
+void* dev_alloc(size_t bytes, hipStream_t s, bool ordered) {
   void* p = nullptr;
   if (g_alloc) {
     p = g_alloc(bytes, s, g_ctx);
     if (!p) fail(MBL_ENOMEM, "allocator callback returned NULL for " + std::to_string(bytes) + " bytes");
     return p;
   }
-  MBL_HIP(hipMalloc(&p, bytes));
+  if (ordered) {
+    prepare_pool();
+    MBL_HIP(hipMallocAsync(&p, bytes, s));
+  } else {
+    MBL_HIP(hipMalloc(&p, bytes));
+  }
   return p;
 }
 
-void dev_free(void* p, hipStream_t s) {
+void dev_free(void* p, hipStream_t s, bool ordered) {
   if (!p) return;
   if (g_free) {
     g_free(p, s, g_ctx);
     return;
   }
-  (void)hipFree(p);
+  if (ordered)
+    (void)hipFreeAsync(p, s);
+  else
+    (void)hipFree(p);
+}
+
+Ham* create_ham(int L, double Sz, double J, double Delta, const double* h_host, hipStream_t stream) {
+  require(L >= 2 && L <= kMaxL, "L must be in [2, 32]");
+  require(std::isfinite(Sz) && std::isfinite(J) && std::isfinite(Delta), "Sz, J, Delta must be finite");
+  const double two = 2.0 * Sz;
+  require(two == std::round(two), "2*Sz must be an integer");
+  const long long tsz = (long long)std::llround(two);
+  require(((tsz + L) % 2 + 2) % 2 == 0, "2*Sz must have the parity of L");
+  require(std::fabs(Sz) <= 0.5 * L, "|Sz| must be <= L/2");
+  require(h_host != nullptr, "h is NULL");
+  for (int i = 0; i < L; ++i) require(std::isfinite(h_host[i]), "h must be finite");
+  auto* H = new Ham();
+  try {
+    H->L = L;
+    H->nup = (int)((tsz + L) / 2);
+    H->J = J;
+    H->Delta = Delta;
+    H->hsum = 0;
+    for (int i = 0; i < L; ++i) {
+      H->h[i] = h_host[i];
+      H->hsum += h_host[i];
+    }
+    const auto C = pascal_table();
+    H->n = C[L * kPascal + H->nup];
+    build_tables(*H, stream);
+    MBL_HIP(hipStreamSynchronize(stream));
+  } catch (...) {
+    delete H;
+    throw;
+  }
+  return H;
+}
+
+int64_t sector_dim(int L, double Sz) {
+  require(L >= 2 && L <= kMaxL, "L must be in [2, 32]");
+  const double two = 2.0 * Sz;
+  require(std::isfinite(Sz) && two == std::round(two), "2*Sz must be an integer");
+  const long long tsz = (long long)std::llround(two);
+  require(((tsz + L) % 2 + 2) % 2 == 0 && std::fabs(Sz) <= 0.5 * L, "no such sector");
+  const auto C = pascal_table();
+  return C[L * kPascal + (int)((tsz + L) / 2)];
 }
 
 }  // namespace mbl
@@ -92,34 +163,7 @@ mbl_status mbl_hamiltonian_create(int L, double Sz, double J, double Delta, cons
   return guard([&] {
     require(out != nullptr, "out is NULL");
     *out = nullptr;
-    require(L >= 2 && L <= kMaxL, "L must be in [2, 32]");
-    require(std::isfinite(Sz) && std::isfinite(J) && std::isfinite(Delta), "Sz, J, Delta must be finite");
-    const double two = 2.0 * Sz;
-    require(two == std::round(two), "2*Sz must be an integer");
-    const long long tsz = (long long)std::llround(two);
-    require(((tsz + L) % 2 + 2) % 2 == 0, "2*Sz must have the parity of L");
-    require(std::fabs(Sz) <= 0.5 * L, "|Sz| must be <= L/2");
-    require(h_host != nullptr, "h is NULL");
-    for (int i = 0; i < L; ++i) require(std::isfinite(h_host[i]), "h must be finite");
-    auto* H = new Ham();
-    try {
-      H->L = L;
-      H->nup = (int)((tsz + L) / 2);
-      H->J = J;
-      H->Delta = Delta;
-      H->hsum = 0;
-      for (int i = 0; i < L; ++i) {
-        H->h[i] = h_host[i];
-        H->hsum += h_host[i];
-      }
-      const auto C = pascal_table();
-      H->n = C[L * kPascal + H->nup];
-      build_tables(*H, stream);
-      MBL_HIP(hipStreamSynchronize(stream));
-    } catch (...) {
-      delete H;
-      throw;
-    }
+    Ham* H = create_ham(L, Sz, J, Delta, h_host, stream);
     *out = reinterpret_cast<mbl_ham>(H);
     return MBL_OK;
   });
@@ -240,6 +284,7 @@ mbl_status mbl_pcg(mbl_ham h, double sigma, mbl_precision prec, const void* R, i
       launch_jacobi<float>(H, sigma, jac.as<float>(), s);
       run_pcg<float>(H, sigma, jac.as<float>(), static_cast<const float*>(R), ldr, static_cast<float*>(W), ldw, b, m, s);
     }
+    MBL_HIP(hipStreamSynchronize(s));
     return MBL_OK;
   });
 }
@@ -332,6 +377,68 @@ mbl_status mbl_lobpcg_solve(mbl_ham h, double sigma, int nev, int block, double 
     require(o.max_iter >= 0 && o.pcg_iters >= 0, "negative iteration count");
     if (info) std::memset(info, 0, sizeof(*info));
     return solve_interior(H, sigma, nev, block, tol, o, evals_host, evecs_dev, ldv, resid_host, info, s);
+  });
+}
+
+mbl_status mbl_footprint_bytes(int L, double Sz, int block, int precision, size_t* bytes) {
+  return guard([&] {
+    require(bytes != nullptr, "bytes is NULL");
+    require(block >= 1, "block < 1");
+    require(precision == MBL_F64 || precision == MBL_MIXED || precision == MBL_PCG32, "bad precision");
+    *bytes = solve_footprint(L, Sz, block, precision);
+    return MBL_OK;
+  });
+}
+
+mbl_status mbl_batch_solve(int count, const mbl_problem* problems, mbl_result* results,
+                           int concurrency) {
+  return guard([&] {
+    require(count >= 0, "count < 0");
+    if (count == 0) return MBL_OK;
+    require(problems != nullptr && results != nullptr, "NULL arrays");
+    require(concurrency >= 1, "concurrency < 1");
+    return batch_solve(count, problems, results, concurrency);
+  });
+}
+
+struct mbl_server_s {};
+
+mbl_status mbl_server_create(int concurrency, size_t hbm_budget, mbl_server* out) {
+  return guard([&] {
+    require(out != nullptr, "out is NULL");
+    require(concurrency >= 1 && concurrency <= 64, "concurrency must be in [1, 64]");
+    Server* srv = nullptr;
+    server_create(concurrency, hbm_budget, &srv);
+    *out = reinterpret_cast<mbl_server>(srv);
+    return MBL_OK;
+  });
+}
+
+mbl_status mbl_server_submit(mbl_server srv, const mbl_problem* request, uint64_t* ticket) {
+  return guard([&] {
+    require(srv && request && ticket, "NULL argument");
+    return server_submit(reinterpret_cast<Server*>(srv), request, ticket);
+  });
+}
+
+mbl_status mbl_server_wait(mbl_server srv, uint64_t ticket, double timeout_s, mbl_result* out) {
+  return guard([&] {
+    require(srv && out, "NULL argument");
+    return server_wait(reinterpret_cast<Server*>(srv), ticket, timeout_s, out);
+  });
+}
+
+mbl_status mbl_server_stats_get(mbl_server srv, mbl_server_stats* st) {
+  return guard([&] {
+    require(srv && st, "NULL argument");
+    return server_stats(reinterpret_cast<Server*>(srv), st);
+  });
+}
+
+mbl_status mbl_server_destroy(mbl_server srv) {
+  return guard([&] {
+    if (srv) server_destroy(reinterpret_cast<Server*>(srv));
+    return MBL_OK;
   });
 }
 

@@ -575,86 +575,119 @@ PcgTiming::~PcgTiming() {
   for (auto& e : ev) (void)hipEventDestroy(e);
 }
 
+// Columns of the block CG are independent, so the block can be solved one
+// column chunk at a time; only the summation order of the dot products can
+// change (the lane layout depends on the chunk width).  The chunk width is
+// chosen so that the chunk's working set (r, p, T, x: 4 n w s bytes) fits a
+// cache budget (MBL_PCG_CACHE_MB; off by default: measured slower at L = 20,
+// where narrow chunks cost more per row than the cache saves).  When even a
+// chunk of 64-byte rows does not fit, the whole block is one chunk.
+template <class T>
+int pcg_chunk_width(int64_t n, int b) {
+  const char* env = std::getenv("MBL_PCG_CACHE_MB");
+  const double budget = 1e6 * std::max(0.0, env ? std::atof(env) : 0.0);
+  const int min_w = std::max(1, 64 / (int)sizeof(T));
+  const double per_col = 4.0 * (double)n * sizeof(T) + 16.0 * n / std::max(1, b);
+  int w = 1;
+  while (w * 2 <= b && (double)(w * 2) * per_col <= budget) w *= 2;
+  if (w < min_w || (double)w * per_col > budget) return b;
+  return w;
+}
+
 template <class T>
 void run_pcg(const Ham& H, double sigma, const T* jac, const T* R, int64_t ldr, T* W, int64_t ldw,
              int b, int m, hipStream_t s, PcgTiming* tm) {
   const int64_t n = H.n;
   if (n == 0 || b == 0) return;
-  DevBuf rbuf((size_t)n * b * sizeof(T), s), pbuf((size_t)n * b * sizeof(T), s),
-      tbuf((size_t)n * b * sizeof(T), s);
-  DevBuf part((size_t)kMaxWg * std::min(b, 4096) * sizeof(double) + 64, s);
+  const int wc = pcg_chunk_width<T>(n, b);
+  DevBuf rbuf((size_t)n * wc * sizeof(T), s), pbuf((size_t)n * wc * sizeof(T), s),
+      tbuf((size_t)n * wc * sizeof(T), s);
+  DevBuf xbuf;
+  if (wc < b) xbuf.reset((size_t)n * wc * sizeof(T), s);
+  DevBuf part((size_t)kMaxWg * std::min(wc, 4096) * sizeof(double) + 64, s);
   DevBuf coefb((size_t)b * sizeof(PcgCoef), s);
   T* r = rbuf.as<T>();
   T* p = pbuf.as<T>();
   T* t = tbuf.as<T>();
   PcgCoef* coef = coefb.as<PcgCoef>();
-  const bool aligned = al16(R, ldr, sizeof(T)) && al16(W, ldw, sizeof(T)) && al16(r, b, sizeof(T));
-  const auto chunks = plan_chunks<T>(b, aligned);
-  for (const Chunk& ch : chunks) {
-    if ((size_t)ch.w * kMaxWg * sizeof(double) > part.bytes()) fail(MBL_EINTERNAL, "pcg: part");
-    const Grid g = make_grid(n, ch.log2G);
-    EltArgs<T> e{};
-    e.R = R;
-    e.ldR = ldr;
-    e.x = W;
-    e.ldxv = ldw;
-    e.r = r;
-    e.ldr = b;
-    e.p = p;
-    e.ldp = b;
-    e.jac = jac;
-    e.coef = coef;
-    e.part = part.as<double>();
-    e.n = n;
-    dispatch_elt<T, ELT_INIT>(ch, g, e, s);
-    finalize<FIN_INIT>(ch, g, part.as<double>(), coef, s);
+  for (int c0 = 0; c0 < b; c0 += wc) {
+    const int w = std::min(wc, b - c0);
+    // chunk views: inputs/outputs of the caller, compact CG vectors (ld = w)
+    const T* Rc = R + c0;
+    T* x = (wc < b) ? xbuf.as<T>() : W;
+    const int64_t ldx = (wc < b) ? w : ldw;
+    PcgCoef* cf = coef + c0;
+    const bool aligned = al16(Rc, ldr, sizeof(T)) && al16(x, ldx, sizeof(T)) && al16(r, w, sizeof(T));
+    for (const Chunk& ch : plan_chunks<T>(w, aligned)) {
+      if ((size_t)ch.w * kMaxWg * sizeof(double) > part.bytes()) fail(MBL_EINTERNAL, "pcg: part");
+      const Grid g = make_grid(n, ch.log2G);
+      EltArgs<T> e{};
+      e.R = Rc;
+      e.ldR = ldr;
+      e.x = x;
+      e.ldxv = ldx;
+      e.r = r;
+      e.ldr = w;
+      e.p = p;
+      e.ldp = w;
+      e.jac = jac;
+      e.coef = cf;
+      e.part = part.as<double>();
+      e.n = n;
+      dispatch_elt<T, ELT_INIT>(ch, g, e, s);
+      finalize<FIN_INIT>(ch, g, part.as<double>(), cf, s);
 
-    ApplyArgs<T> a1 = base_args<T>(H, sigma);  // T = (H - sigma) p, |T|^2
-    a1.X = p;
-    a1.ldx = b;
-    a1.Y = t;
-    a1.ldy = b;
-    a1.part = part.as<double>();
-    ApplyArgs<T> a2 = base_args<T>(H, sigma);  // q = (H - sigma) T, CG update
-    a2.X = t;
-    a2.ldx = b;
-    a2.x = W;
-    a2.ldxv = ldw;
-    a2.r = r;
-    a2.ldr = b;
-    a2.p = p;
-    a2.ldp = b;
-    a2.jac = jac;
-    a2.coef = coef;
-    a2.part = part.as<double>();
-    const int ntimed = tm ? std::min(m, PcgTiming::kSample) : 0;
-    if (tm) tm->init();
-    for (int it = 0; it < m; ++it) {
-      const bool timed = it < ntimed;
-      if (timed) MBL_HIP(hipEventRecord(tm->ev[4 * it + 0], s));
-      dispatch_apply<T, EPI_NORM2>(ch, g, a1, s);
-      if (timed) MBL_HIP(hipEventRecord(tm->ev[4 * it + 1], s));
-      finalize<FIN_ALPHA>(ch, g, part.as<double>(), coef, s);
-      if (timed) MBL_HIP(hipEventRecord(tm->ev[4 * it + 2], s));
-      dispatch_apply<T, EPI_PCG>(ch, g, a2, s);
-      if (timed) MBL_HIP(hipEventRecord(tm->ev[4 * it + 3], s));
-      finalize<FIN_BETA>(ch, g, part.as<double>(), coef, s);
-      dispatch_elt<T, ELT_PUPD>(ch, g, e, s);
-    }
-    if (ntimed > 0) {
-      MBL_HIP(hipStreamSynchronize(s));
-      for (int it = 0; it < ntimed; ++it) {
-        float a = 0.f, c = 0.f;
-        MBL_HIP(hipEventElapsedTime(&a, tm->ev[4 * it + 0], tm->ev[4 * it + 1]));
-        MBL_HIP(hipEventElapsedTime(&c, tm->ev[4 * it + 2], tm->ev[4 * it + 3]));
-        tm->ms[0] += a;
-        tm->ms[1] += c;
+      ApplyArgs<T> a1 = base_args<T>(H, sigma);  // T = (H - sigma) p, |T|^2
+      a1.X = p;
+      a1.ldx = w;
+      a1.Y = t;
+      a1.ldy = w;
+      a1.part = part.as<double>();
+      ApplyArgs<T> a2 = base_args<T>(H, sigma);  // q = (H - sigma) T, CG update
+      a2.X = t;
+      a2.ldx = w;
+      a2.x = x;
+      a2.ldxv = ldx;
+      a2.r = r;
+      a2.ldr = w;
+      a2.p = p;
+      a2.ldp = w;
+      a2.jac = jac;
+      a2.coef = cf;
+      a2.part = part.as<double>();
+      const int ntimed = tm ? std::min(m, PcgTiming::kSample) : 0;
+      if (tm) tm->init();
+      for (int it = 0; it < m; ++it) {
+        const bool timed = it < ntimed;
+        if (timed) MBL_HIP(hipEventRecord(tm->ev[4 * it + 0], s));
+        dispatch_apply<T, EPI_NORM2>(ch, g, a1, s);
+        if (timed) MBL_HIP(hipEventRecord(tm->ev[4 * it + 1], s));
+        finalize<FIN_ALPHA>(ch, g, part.as<double>(), cf, s);
+        if (timed) MBL_HIP(hipEventRecord(tm->ev[4 * it + 2], s));
+        dispatch_apply<T, EPI_PCG>(ch, g, a2, s);
+        if (timed) MBL_HIP(hipEventRecord(tm->ev[4 * it + 3], s));
+        finalize<FIN_BETA>(ch, g, part.as<double>(), cf, s);
+        dispatch_elt<T, ELT_PUPD>(ch, g, e, s);
       }
-      tm->launches[0] += ntimed;
-      tm->launches[1] += ntimed;
+      if (ntimed > 0) {
+        MBL_HIP(hipStreamSynchronize(s));
+        for (int it = 0; it < ntimed; ++it) {
+          float ta = 0.f, tc = 0.f;
+          MBL_HIP(hipEventElapsedTime(&ta, tm->ev[4 * it + 0], tm->ev[4 * it + 1]));
+          MBL_HIP(hipEventElapsedTime(&tc, tm->ev[4 * it + 2], tm->ev[4 * it + 3]));
+          tm->ms[0] += ta;
+          tm->ms[1] += tc;
+        }
+        tm->launches[0] += ntimed;
+        tm->launches[1] += ntimed;
+        tm->bytes[0] += (double)ntimed * (2.0 * n * ch.w * sizeof(T) + 12.0 * n);
+        tm->bytes[1] += (double)ntimed * (6.0 * n * ch.w * sizeof(T) + (12.0 + sizeof(T)) * n);
+      }
     }
+    if (wc < b)
+      MBL_HIP(hipMemcpy2DAsync(W + c0, ldw * sizeof(T), x, w * sizeof(T), w * sizeof(T), n,
+                               hipMemcpyDeviceToDevice, s));
   }
-  MBL_HIP(hipStreamSynchronize(s));  // work buffers are freed on return
 }
 
 template void launch_apply<double>(const Ham&, double, const double*, int64_t, double*, int64_t,

@@ -231,7 +231,6 @@ void launch_gram(int64_t n, const T* A, int64_t lda, int p, const T* B, int64_t 
   hipLaunchKernelGGL(k_gram_fold, dim3((unsigned)(((int64_t)p * q + 3) / 4)), dim3(256), 0, s,
                      part.as<double>(), (int)splits, p, q, C, ldc);
   MBL_CHECK_LAUNCH();
-  MBL_HIP(hipStreamSynchronize(s));  // `part` is released on return
 }
 
 template <class T>

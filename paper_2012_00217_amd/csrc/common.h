@@ -34,9 +34,11 @@ struct Error : std::runtime_error {
 
 #define MBL_CHECK_LAUNCH() MBL_HIP(hipGetLastError())
 
-// Device allocation through the installed callback (or hipMalloc).
-void* dev_alloc(size_t bytes, hipStream_t s);
-void dev_free(void* p, hipStream_t s);
+// Device allocation through the installed callback, else hipMallocAsync on
+// the stream (`ordered`: work buffers, freed stream-ordered so concurrent
+// solves never wait on a device-wide free) or hipMalloc (long-lived tables).
+void* dev_alloc(size_t bytes, hipStream_t s, bool ordered);
+void dev_free(void* p, hipStream_t s, bool ordered);
 
 // Owning device buffer.
 class DevBuf {
@@ -46,19 +48,24 @@ class DevBuf {
   ~DevBuf() { release(); }
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : p_(o.p_), n_(o.n_), s_(o.s_) { o.p_ = nullptr; o.n_ = 0; }
+  DevBuf(DevBuf&& o) noexcept : p_(o.p_), n_(o.n_), s_(o.s_), ordered_(o.ordered_) {
+    o.p_ = nullptr;
+    o.n_ = 0;
+  }
   DevBuf& operator=(DevBuf&& o) noexcept {
-    if (this != &o) { release(); p_ = o.p_; n_ = o.n_; s_ = o.s_; o.p_ = nullptr; o.n_ = 0; }
+    if (this != &o) {
+      release();
+      p_ = o.p_; n_ = o.n_; s_ = o.s_; ordered_ = o.ordered_;
+      o.p_ = nullptr; o.n_ = 0;
+    }
     return *this;
   }
-  void reset(size_t bytes, hipStream_t s) {
-    release();
-    s_ = s;
-    if (bytes) p_ = dev_alloc(bytes, s);
-    n_ = bytes;
-  }
+  // stream-ordered work buffer
+  void reset(size_t bytes, hipStream_t s) { alloc(bytes, s, true); }
+  // long-lived buffer (outlives the stream it was made on)
+  void reset_persistent(size_t bytes) { alloc(bytes, nullptr, false); }
   void release() {
-    if (p_) dev_free(p_, s_);
+    if (p_) dev_free(p_, s_, ordered_);
     p_ = nullptr;
     n_ = 0;
   }
@@ -67,9 +74,17 @@ class DevBuf {
   size_t bytes() const { return n_; }
 
  private:
+  void alloc(size_t bytes, hipStream_t s, bool ordered) {
+    release();
+    s_ = s;
+    ordered_ = ordered;
+    if (bytes) p_ = dev_alloc(bytes, s, ordered);
+    n_ = bytes;
+  }
   void* p_ = nullptr;
   size_t n_ = 0;
   hipStream_t s_ = nullptr;
+  bool ordered_ = true;
 };
 
 // Per-sector Hamiltonian data (the opaque mbl_ham).
@@ -110,6 +125,7 @@ struct PcgTiming {
   bool ready = false;
   int64_t launches[2] = {0, 0};
   double ms[2] = {0, 0};
+  double bytes[2] = {0, 0};  // algorithmic bytes of the timed launches
   void init();
   ~PcgTiming();
 };
@@ -155,5 +171,20 @@ mbl_status solve_interior(const Ham& H, double sigma, int nev, int b, double tol
                           const mbl_solve_opts& o, double* evals, double* evecs, int64_t ldv,
                           double* resid, mbl_solve_info* info, hipStream_t s);
 mbl_status spectrum_bounds(const Ham& H, double tol, double* emin, double* emax, hipStream_t s);
+
+// Validated construction of a sector handle (throws Error on bad input).
+Ham* create_ham(int L, double Sz, double J, double Delta, const double* h_host, hipStream_t s);
+// Sector dimension C(L, Sz + L/2) (throws Error for a sector that does not exist).
+int64_t sector_dim(int L, double Sz);
+
+// Independent solves (service.hip).
+size_t solve_footprint(int L, double Sz, int b, int prec);
+mbl_status batch_solve(int count, const mbl_problem* probs, mbl_result* res, int conc);
+struct Server;
+mbl_status server_create(int conc, size_t budget, Server** out);
+mbl_status server_submit(Server* srv, const mbl_problem* rq, uint64_t* ticket);
+mbl_status server_wait(Server* srv, uint64_t ticket, double timeout_s, mbl_result* out);
+mbl_status server_stats(Server* srv, mbl_server_stats* st);
+void server_destroy(Server* srv);
 
 }  // namespace mbl

@@ -322,6 +322,7 @@ class Phase {
       PcgTiming* tm = st_.timing ? &st_.tm[sizeof(TP) == 4 ? 1 : 0] : nullptr;
       if constexpr (std::is_same<TB, TP>::value) {
         run_pcg<TP>(H_, p_.sigma, jac, R, b, W, ld, b, m, s_, tm);
+        MBL_HIP(hipStreamSynchronize(s_));
       } else {
         DevBuf rp((size_t)n * b * sizeof(TP), s_), wp((size_t)n * b * sizeof(TP), s_);
         launch_convert<TB, TP>(n, b, R, b, rp.as<TP>(), b, s_);
@@ -549,6 +550,8 @@ mbl_status solve_interior(const Ham& H, double sigma, int nev, int b, double tol
       info->cg_apply2_launches[k] = st.tm[k].launches[1];
       info->cg_apply1_ms[k] = st.tm[k].ms[0];
       info->cg_apply2_ms[k] = st.tm[k].ms[1];
+      info->cg_apply1_bytes[k] = st.tm[k].bytes[0];
+      info->cg_apply2_bytes[k] = st.tm[k].bytes[1];
     }
   }
   return ok ? MBL_OK : MBL_ENOCONV;

@@ -170,6 +170,22 @@ def test_pcg_parity(m, b):
         np.testing.assert_allclose(W, Wr, rtol=0, atol=1e-9 * np.abs(Wr).max())
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_pcg_column_chunks_agree(dtype, monkeypatch):
+    """Solving the block CG in cache-sized column chunks (ragged last chunk)
+    changes only the rounding order of the dot products."""
+    L = 12
+    h, H = _ham(L)
+    R = torch.from_numpy(workloads.random_block(H.n, 40, seed=8)).to(DEV, dtype)
+    monkeypatch.setenv("MBL_PCG_CACHE_MB", "0")
+    W_full = H.pcg(R, 0.05, 6)
+    monkeypatch.setenv("MBL_PCG_CACHE_MB", "0.3")
+    W_chunk = H.pcg(R, 0.05, 6)
+    tol = 1e-11 if dtype == torch.float64 else 1e-4
+    assert torch.allclose(W_full, W_chunk, rtol=tol, atol=tol * W_full.abs().max().item())
+    assert not torch.equal(W_full, torch.zeros_like(W_full))
+
+
 def test_pcg_fp32_close_to_fp64():
     L = 14
     h, H = _ham(L, W=4.0)

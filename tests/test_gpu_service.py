@@ -1,0 +1,87 @@
+"""Batch and serving entry points: results equal the single-solve path
+(bitwise: every solve is a deterministic kernel sequence), parity with the
+oracle on a stratified sample, footprint admission and server statistics."""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import hamiltonian, linalg, spectrum
+from paper_2012_00217_amd import workloads
+
+pytestmark = pytest.mark.gpu
+api = pytest.importorskip("paper_2012_00217_amd.api")
+
+
+def _problems():
+    probs = []
+    for j, (L, W) in enumerate([(12, 2.0), (14, 4.0), (12, 8.0), (14, 6.0), (16, 4.0), (12, 6.0)]):
+        probs.append({"L": L, "h": workloads.disorder(L, W, 100 + j), "eps": 0.5, "nev": 8,
+                      "block": 16, "tol": 1e-10, "precision": "f64", "seed": 7})
+    return probs
+
+
+def test_batch_equals_single_solves_and_oracle():
+    probs = _problems()
+    res = api.batch_solve(probs, concurrency=4, vectors=True)
+    for d, r in zip(probs, res):
+        assert r["status"] == "MBL_OK", r
+        H = api.Hamiltonian(d["L"], d["h"])
+        ev, V, rs, info = H.solve(r["sigma"], d["nev"], d["block"], tol=d["tol"], seed=d["seed"])
+        assert np.array_equal(ev, r["evals"]) and torch.equal(V, r["evecs"])
+        st, Ho = hamiltonian.sector_matrix(d["L"], d["L"] // 2, 1.0, 1.0, d["h"])
+        w_ref, _ = spectrum.nearest(Ho, r["sigma"], d["nev"])
+        assert np.max(np.abs(r["evals"] - w_ref)) <= 1e-10
+        assert np.max(linalg.residual_norms(Ho, r["evals"], r["evecs"].cpu().numpy())) <= 1e-10
+        lo, hi = spectrum.bounds(Ho)
+        assert abs(r["sigma"] - (lo + 0.5 * (hi - lo))) < 1e-9
+
+
+def test_batch_reports_per_problem_errors():
+    probs = _problems()[:2]
+    probs[1]["nev"] = 40  # nev > block
+    res = api.batch_solve(probs, concurrency=2)
+    assert res[0]["status"] == "MBL_OK"
+    assert res[1]["status"] == "MBL_EINVAL"
+
+
+def test_server_results_equal_alone_and_in_the_mix():
+    probs = _problems()
+    with api.Server(concurrency=3) as srv:
+        tickets = [srv.submit(dict(d, want_vectors=True)) for d in probs]
+        outs = []
+        for t, d in zip(tickets, probs):
+            V = torch.empty((api.Hamiltonian(d["L"], d["h"]).n, d["nev"]), dtype=torch.float64,
+                            device="cuda")
+            r = srv.wait(t, vectors_out=V)
+            outs.append((r, V))
+        st = srv.stats()
+    assert st["completed"] == len(probs) and st["rejected"] == 0
+    assert 0 < st["p50_latency"] <= st["p99_latency"]
+    alone = api.batch_solve(probs, concurrency=1, vectors=True)
+    for (r, V), a in zip(outs, alone):
+        assert r["status"] == "MBL_OK"
+        assert np.array_equal(r["evals"], a["evals"]) and torch.equal(V, a["evecs"])
+
+
+def test_server_admission_refuses_oversized_request():
+    d = _problems()[0]
+    budget = api.footprint_bytes(14, 16, "f64") + 1000
+    with api.Server(concurrency=2, hbm_budget=budget) as srv:
+        t_small = srv.submit(d)  # L=12 fits
+        with pytest.raises(api.MblError) as e:
+            srv.submit(dict(d, L=16, h=workloads.disorder(16, 4.0, 1)))
+        assert "exceeds the budget" in str(e.value)
+        r = srv.wait(t_small)
+        assert r["status"] == "MBL_OK"
+        assert srv.stats()["rejected"] == 1
+        assert srv.stats()["peak_bytes"] <= budget
+
+
+def test_server_wait_timeout_returns_none():
+    d = dict(_problems()[4], L=18, h=workloads.disorder(18, 4.0, 3), nev=16, block=32)
+    with api.Server(concurrency=1) as srv:
+        t = srv.submit(d)
+        assert srv.wait(t, timeout=0.0) is None
+        r = srv.wait(t)
+        assert r["status"] == "MBL_OK"
