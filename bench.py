@@ -117,12 +117,105 @@ def cpu_baseline(wl, gpu_runs):
     }
 
 
+def run_batch(args):
+    """256 disorder realisations of mixed L (the batched workload): one step is
+    one mbl_batch_solve over all problems, `--concurrency` at a time; the same
+    problems one at a time give the single-solve comparison."""
+    import numpy as np
+    import torch
+    from paper_2012_00217_amd import api, workloads
+
+    probs = []
+    for p in workloads.batch_problems(args.count):
+        probs.append({"L": p["L"], "h": p["h"], "eps": 0.5, "nev": 16, "block": 32, "tol": 1e-10,
+                      "precision": "f64", "seed": 7})
+    torch.cuda.init()
+    api.batch_solve(probs[:2], concurrency=2)  # load kernels
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = api.batch_solve(probs, concurrency=args.concurrency)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    pairs = sum(int(np.sum(r["resid"] <= 1e-10)) for r in res if r["status"] == "MBL_OK")
+    out = {"metric": "eigenpairs/s at resid<=1e-10 (batched)", "value": round(pairs / el, 3),
+           "unit": "eigenpairs/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+           "ms_per_step": round(el * 1e3, 1), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"{args.count} realisations, L in {{14,16,18}} (Sz=0), W in "
+                                  "{2,4,6,8} from seed j, 16 pairs nearest energy density 0.5, "
+                                  "block 32, tol 1e-10, FP64",
+                      "concurrency": args.concurrency, "pairs": pairs,
+                      "failed": sum(r["status"] != "MBL_OK" for r in res)}}
+    if args.plain:
+        t0 = time.perf_counter()
+        res1 = api.batch_solve(probs, concurrency=1)
+        el1 = time.perf_counter() - t0
+        p1 = sum(int(np.sum(r["resid"] <= 1e-10)) for r in res1 if r["status"] == "MBL_OK")
+        same = all(np.array_equal(a["evals"], b["evals"]) for a, b in zip(res, res1))
+        out["plain"] = {"value": round(p1 / el1, 3), "ms": round(el1 * 1e3, 1),
+                        "identical_results": same}
+    print(json.dumps(out), flush=True)
+
+
+def run_serve(args):
+    """Open-loop request stream: Poisson arrivals of solves with mixed L, W and
+    energy density, served with continuous batching; p50/p99 latency."""
+    import numpy as np
+    import torch
+    from paper_2012_00217_amd import api, workloads
+
+    Ls = tuple(int(x) for x in args.serve_L.split(","))
+    reqs = workloads.request_stream(args.count, rate_hz=1.0, Ls=Ls)
+    probs = [{"L": r["L"], "h": r["h"], "eps": r["eps"], "nev": 16, "block": 32, "tol": 1e-10,
+              "precision": args.serve_precision, "seed": 7} for r in reqs]
+    torch.cuda.init()
+    api.batch_solve(probs[:2], concurrency=2)
+    # closed-loop capacity: all requests at once
+    t0 = time.perf_counter()
+    api.batch_solve(probs, concurrency=args.concurrency)
+    cap = len(probs) / (time.perf_counter() - t0)
+    rate = args.load * cap
+    gaps = np.random.default_rng(args.count).exponential(1.0 / rate, len(probs))
+    results = [None] * len(probs)
+    with api.Server(concurrency=args.concurrency) as srv:
+        t0 = time.perf_counter()
+        tickets_ready = []
+        for i, d in enumerate(probs):
+            time.sleep(gaps[i])
+            tickets_ready.append(srv.submit(d))
+        for i, t in enumerate(tickets_ready):
+            results[i] = srv.wait(t)
+        el = time.perf_counter() - t0
+        st = srv.stats()
+    lat = np.array([r["latency"] for r in results])
+    pairs = sum(int(np.sum(r["resid"] <= 1e-10)) for r in results if r["status"] == "MBL_OK")
+    out = {"metric": "p99 ms (serving)", "value": round(float(np.percentile(lat, 99)) * 1e3, 1),
+           "unit": "ms", "higher_is_better": False, "n_gpus": 1, "steps": 1, "warmup": 0,
+           "ms_per_step": round(el * 1e3, 1), "scaling": "weak", "vs_baseline": None,
+           "dtype": args.serve_precision, "data": "synthetic",
+           "config": {"workload": f"{len(probs)} Poisson requests at {args.load:g} x closed-loop "
+                                  f"capacity ({rate:.3f}/s), L in {Ls} (Sz=0), W~U[1,10], "
+                                  "energy density in {0.1,0.5,0.9}, 16 pairs, block 32, tol 1e-10",
+                      "concurrency": args.concurrency},
+           "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 1),
+           "throughput_pairs_per_s": round(pairs / el, 3),
+           "capacity_req_per_s": round(cap, 4),
+           "server_stats": {k: st[k] for k in ("completed", "rejected", "peak_bytes")}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=0)
-    ap.add_argument("--workload", default="l20", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="l20", choices=sorted(WORKLOADS) + ["batch", "serve"])
+    ap.add_argument("--count", type=int, default=256, help="batch/serve: number of problems")
+    ap.add_argument("--concurrency", type=int, default=8, help="batch/serve: concurrent solves")
+    ap.add_argument("--plain", action="store_true", help="batch: also solve one at a time")
+    ap.add_argument("--serve-L", default="16,18,20")
+    ap.add_argument("--serve-precision", default="mixed")
+    ap.add_argument("--load", type=float, default=0.8, help="serve: arrival rate / capacity")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cg-only", type=int, default=0,
                     help="counter runs: only run this many CG steps per realisation")
@@ -131,6 +224,11 @@ def main():
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "batch":
+        return run_batch(args)
+    if args.workload == "serve":
+        return run_serve(args)
 
     import numpy as np
     import torch
