@@ -26,6 +26,8 @@ What the oracle computes, from the definitions in the paper:
                      the fold, step by step, per column (Sec. 3.2).
 * ``linalg``      -- Gram products, Cholesky-QR, residual norms and cluster
                      subspace angles used to compare results.
+* ``observables`` -- adjacent gap ratio and half-chain entanglement entropy
+                     of eigenpairs (Sec. 2.2).
 
 Conventions where the paper is silent (each is also listed with its reason in
 the design notes):
@@ -41,4 +43,4 @@ prints (Table 1), closed forms, an independent tensor-product construction of
 eq. (2), or brute force.  Anything not pinned says so in its docstring.
 """
 
-from . import basis, hamiltonian, spectrum, freefermion, pcg, linalg  # noqa: F401
+from . import basis, hamiltonian, spectrum, freefermion, pcg, linalg, observables  # noqa: F401
