@@ -207,6 +207,27 @@ mbl_status mbl_lobpcg_solve(mbl_ham H, double sigma, int nev, int block,
                             double* resid_host, mbl_solve_info* info,
                             hipStream_t stream);
 
+/* ---- MBL observables and spectrum slices (paper Sec. 2.2, 3.1) ----------- */
+
+/* Von Neumann entanglement entropy (natural log) of each of the nev unit
+ * eigenvectors (device, n x nev FP64, ld ldv) across the cut between sites
+ * cut-1 and cut (left part: sites 0..cut-1).  1 <= cut <= L-1 and
+ * L - cut <= 26.  S_host[nev].  Synchronises `stream`. */
+mbl_status mbl_entanglement_entropy(mbl_ham H, const double* V_dev, int64_t ldv, int nev,
+                                    int cut, double* S_host, hipStream_t stream);
+
+/* Mean adjacent gap ratio <min(d_n, d_n+1) / max(d_n, d_n+1)> of `count`
+ * eigenvalues (host; sorted internally; count >= 3). */
+mbl_status mbl_gap_ratio(const double* evals_host, int count, double* mean_r);
+
+/* Eigenvalue chunks of one H: for each of `count` shifts, the nev eigenpairs
+ * nearest it (as mbl_lobpcg_solve, eigenvalues and residuals only), solved
+ * `concurrency` at a time on worker streams sharing the handle.
+ * evals_host[count*nev], resid_host[count*nev] (may be NULL). */
+mbl_status mbl_slices_solve(mbl_ham H, int count, const double* sigmas_host, int nev, int block,
+                            double tol, const mbl_solve_opts* opts, double* evals_host,
+                            double* resid_host, int concurrency);
+
 /* ---- many independent solves (paper Sec. 3.1: realisations, disorder
  * strengths and spectral regions are independent levels of concurrency) ---- */
 

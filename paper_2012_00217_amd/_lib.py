@@ -82,6 +82,10 @@ PROTOTYPES = {
     "mbl_lobpcg_solve": (cint, [vp, dbl, cint, cint, dbl, C.POINTER(SolveOpts), dptr, vp, i64,
                                 dptr, C.POINTER(SolveInfo), vp]),
     "mbl_footprint_bytes": (cint, [cint, dbl, cint, cint, C.POINTER(C.c_size_t)]),
+    "mbl_entanglement_entropy": (cint, [vp, vp, i64, cint, cint, dptr, vp]),
+    "mbl_gap_ratio": (cint, [dptr, cint, dptr]),
+    "mbl_slices_solve": (cint, [vp, cint, dptr, cint, cint, dbl, C.POINTER(SolveOpts), dptr, dptr,
+                                cint]),
     "mbl_batch_solve": (cint, [cint, C.POINTER(Problem), C.POINTER(Result), cint]),
     "mbl_server_create": (cint, [cint, C.c_size_t, C.POINTER(vp)]),
     "mbl_server_submit": (cint, [vp, C.POINTER(Problem), C.POINTER(C.c_uint64)]),

@@ -129,6 +129,36 @@ class Hamiltonian:
                                                    _stream(stream)))
         return lo.value, hi.value
 
+    def entanglement_entropy(self, V, cut=None, stream=None):
+        """Entanglement entropy of each column of V (n x nev FP64) across the
+        cut after `cut` sites (default: half chain)."""
+        cut = self.L // 2 if cut is None else int(cut)
+        pv, ldv = _block(V, "V")
+        if V.dtype != torch.float64:
+            raise TypeError("V must be float64")
+        S = np.zeros(V.shape[1])
+        _lib.check(_lib.load().mbl_entanglement_entropy(self._h, pv, ldv, V.shape[1], cut,
+                                                        S.ctypes.data_as(_lib.dptr),
+                                                        _stream(stream)))
+        return S
+
+    def solve_slices(self, sigmas, nev, block, tol=1e-10, precision="f64", concurrency=4,
+                     max_iter=400, pcg_iters=0, seed=0x5EED):
+        """Eigenvalue chunks: the nev pairs nearest each shift (values and residuals)."""
+        lib = _lib.load()
+        sig = np.ascontiguousarray(np.asarray(sigmas, dtype=np.float64))
+        opts = _lib.SolveOpts()
+        _lib.check(lib.mbl_solve_opts_default(C.byref(opts)))
+        opts.max_iter, opts.pcg_iters, opts.seed = int(max_iter), int(pcg_iters), int(seed)
+        opts.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        ev = np.zeros((len(sig), nev))
+        rs = np.zeros((len(sig), nev))
+        _lib.check(lib.mbl_slices_solve(self._h, len(sig), sig.ctypes.data_as(_lib.dptr), int(nev),
+                                        int(block), float(tol), C.byref(opts),
+                                        ev.ctypes.data_as(_lib.dptr),
+                                        rs.ctypes.data_as(_lib.dptr), int(concurrency)))
+        return ev, rs
+
     def solve(self, sigma, nev, block, tol=1e-10, precision="f64", max_iter=400, pcg_iters=0,
               seed=0x5EED, verbose=False, want_vectors=True, device="cuda", stream=None,
               raise_on_noconv=True, timing=False):
@@ -232,6 +262,14 @@ def _result_dict(r, ev, rs):
             "nconv": r.nconv, "iters": r.iters, "applies": r.applies,
             "max_resid": r.max_resid, "seconds": r.seconds, "latency": r.latency,
             "evals": ev, "resid": rs}
+
+
+def gap_ratio(evals):
+    """Mean adjacent gap ratio of a set of eigenvalues (library host routine)."""
+    e = np.ascontiguousarray(np.asarray(evals, dtype=np.float64))
+    out = C.c_double()
+    _lib.check(_lib.load().mbl_gap_ratio(e.ctypes.data_as(_lib.dptr), len(e), C.byref(out)))
+    return out.value
 
 
 def footprint_bytes(L, block, precision="f64", Sz=0.0):

@@ -380,6 +380,48 @@ mbl_status mbl_lobpcg_solve(mbl_ham h, double sigma, int nev, int block, double 
   });
 }
 
+mbl_status mbl_entanglement_entropy(mbl_ham h, const double* V_dev, int64_t ldv, int nev,
+                                    int cut, double* S_host, hipStream_t s) {
+  return guard([&] {
+    const Ham& H = ham(h);
+    require(V_dev && S_host, "NULL argument");
+    require(nev >= 1 && ldv >= nev, "need nev >= 1 and ldv >= nev");
+    require(cut >= 1 && cut <= H.L - 1 && H.L - cut <= 26, "need 1 <= cut <= L-1, L-cut <= 26");
+    entanglement_entropy(H, V_dev, ldv, nev, cut, S_host, s);
+    return MBL_OK;
+  });
+}
+
+mbl_status mbl_gap_ratio(const double* evals_host, int count, double* mean_r) {
+  return guard([&] {
+    require(evals_host && mean_r, "NULL argument");
+    require(count >= 3, "count < 3");
+    for (int i = 0; i < count; ++i) require(std::isfinite(evals_host[i]), "non-finite eigenvalue");
+    *mean_r = mean_gap_ratio(evals_host, count);
+    return MBL_OK;
+  });
+}
+
+mbl_status mbl_slices_solve(mbl_ham h, int count, const double* sigmas_host, int nev, int block,
+                            double tol, const mbl_solve_opts* opts, double* evals_host,
+                            double* resid_host, int concurrency) {
+  return guard([&] {
+    const Ham& H = ham(h);
+    require(count >= 1 && sigmas_host && evals_host, "bad arguments");
+    for (int i = 0; i < count; ++i) require(std::isfinite(sigmas_host[i]), "sigma must be finite");
+    require(nev >= 1 && nev <= block && 2 * (int64_t)block <= H.n && block <= 320, "bad nev/block");
+    require(tol > 0 && std::isfinite(tol), "tol must be > 0");
+    require(concurrency >= 1, "concurrency < 1");
+    mbl_solve_opts o;
+    mbl_solve_opts_default(&o);
+    if (opts) o = *opts;
+    require(o.precision == MBL_F64 || o.precision == MBL_MIXED || o.precision == MBL_PCG32,
+            "bad precision");
+    return solve_slices(H, count, sigmas_host, nev, block, tol, o, evals_host, resid_host,
+                        concurrency);
+  });
+}
+
 mbl_status mbl_footprint_bytes(int L, double Sz, int block, int precision, size_t* bytes) {
   return guard([&] {
     require(bytes != nullptr, "bytes is NULL");

@@ -187,4 +187,11 @@ mbl_status server_wait(Server* srv, uint64_t ticket, double timeout_s, mbl_resul
 mbl_status server_stats(Server* srv, mbl_server_stats* st);
 void server_destroy(Server* srv);
 
+// Observables and spectrum slices (observables.hip).
+void entanglement_entropy(const Ham& H, const double* V, int64_t ldv, int nev, int cut, double* S,
+                          hipStream_t s);
+double mean_gap_ratio(const double* e, int count);
+mbl_status solve_slices(const Ham& H, int count, const double* sigmas, int nev, int b, double tol,
+                        const mbl_solve_opts& o, double* evals, double* resid, int conc);
+
 }  // namespace mbl

@@ -69,3 +69,12 @@ def test_footprint_model():
     assert n28 * 32 * 8 * 17 < big < 288e9
     with pytest.raises(api.MblError):
         api.footprint_bytes(13, 64, "f64", Sz=0.0)
+
+
+def test_gap_ratio_host_routine():
+    import numpy as np
+    from paper_2012_00217_amd import api
+    assert api.gap_ratio([0.0, 1.0, 3.0, 3.5]) == 0.375
+    assert api.gap_ratio(np.arange(12.0)[::-1]) == 1.0
+    with pytest.raises(api.MblError):
+        api.gap_ratio([1.0, 2.0])

@@ -1,0 +1,70 @@
+"""GPU entanglement entropy and spectrum slices against the oracle."""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import basis, hamiltonian, spectrum, freefermion, observables
+from paper_2012_00217_amd import workloads
+
+pytestmark = pytest.mark.gpu
+api = pytest.importorskip("paper_2012_00217_amd.api")
+
+
+@pytest.mark.parametrize("L,cut", [(12, 6), (12, 3), (13, 5), (14, 7)])
+def test_entropy_matches_oracle(L, cut):
+    Sz = 0.0 if L % 2 == 0 else 0.5
+    k = basis.nup_from_sz(L, Sz)
+    h = workloads.disorder(L, 3.0, L)
+    st, Ho = hamiltonian.sector_matrix(L, k, 1.0, 1.0, h)
+    w, V = spectrum.nearest(Ho, 0.0, 5)
+    H = api.Hamiltonian(L, h, Sz=Sz)
+    S = H.entanglement_entropy(torch.from_numpy(np.ascontiguousarray(V)).cuda(), cut)
+    want = [observables.entanglement_entropy(V[:, j], st, L, cut) for j in range(V.shape[1])]
+    np.testing.assert_allclose(S, want, atol=1e-10)
+
+
+def test_entropy_of_free_fermion_eigenstates_half_chain():
+    """Delta = 0 Slater determinants: Peschel's correlation-matrix formula."""
+    L, cut = 14, 7
+    k = L // 2
+    h = workloads.disorder(L, 2.0, 5)
+    st = basis.enumerate_sector(L, k)
+    eps, phi = freefermion.single_particle(L, 1.0, h)
+    _, masks = freefermion.nearest(L, k, 1.0, h, st, 0.0, 4)
+    V = np.stack([freefermion.slater_vector(L, 1.0, h, m, st) for m in masks], axis=1)
+    H = api.Hamiltonian(L, h, Delta=0.0)
+    S = H.entanglement_entropy(torch.from_numpy(V).cuda(), cut)
+    for j, m in enumerate(masks):
+        occ = [q for q in range(L) if (int(m) >> q) & 1]
+        c = np.clip(np.linalg.eigvalsh(phi[:cut, occ] @ phi[:cut, occ].T), 1e-300, 1 - 1e-16)
+        assert S[j] == pytest.approx(-np.sum(c * np.log(c) + (1 - c) * np.log1p(-c)), abs=1e-9)
+
+
+def test_solved_vectors_entropy_and_gap_ratio():
+    L = 14
+    h = workloads.disorder(L, 4.0, 9)
+    st, Ho = hamiltonian.sector_matrix(L, L // 2, 1.0, 1.0, h)
+    H = api.Hamiltonian(L, h)
+    lo, hi = spectrum.bounds(Ho)
+    sigma = spectrum.shift_from_density(lo, hi, 0.5)
+    ev, V, rs, info = H.solve(sigma, 8, 16, tol=1e-10)
+    S = H.entanglement_entropy(V)
+    Vn = V.cpu().numpy()
+    want = [observables.entanglement_entropy(Vn[:, j], st, L, L // 2) for j in range(8)]
+    np.testing.assert_allclose(S, want, atol=1e-9)
+    assert api.gap_ratio(ev) == pytest.approx(np.nanmean(observables.gap_ratios(ev)), abs=1e-15)
+
+
+def test_spectrum_slices_match_oracle():
+    L = 12
+    h = workloads.disorder(L, 6.0, 4)
+    st, Ho = hamiltonian.sector_matrix(L, L // 2, 1.0, 1.0, h)
+    lo, hi = spectrum.bounds(Ho)
+    sig = [spectrum.shift_from_density(lo, hi, e) for e in (0.1, 0.5, 0.9)]
+    H = api.Hamiltonian(L, h)
+    ev, rs = H.solve_slices(sig, 6, 12, concurrency=3)
+    for i, s in enumerate(sig):
+        w, _ = spectrum.nearest(Ho, s, 6)
+        np.testing.assert_allclose(ev[i], w, atol=1e-10)
+        assert np.all(rs[i] <= 1e-10)
