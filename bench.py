@@ -313,7 +313,7 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
                 "kernel": f"k_apply fused CG {dom} ({'FP64' if s == 8 else 'FP32'}, "
-                          f"{wl['block']}-column block in cache-sized column chunks)",
+                          f"{wl['block']}-column block)",
                 "algorithmic_bytes_per_launch": kb, "avg_launch_us": round(avg[dom] * 1e3, 2),
                 "timed_launches": tot[dom][0]}
 

@@ -20,8 +20,9 @@
 //
 // Column reductions (the CG dot products) are accumulated in FP64 per lane,
 // reduced across the wavefront with a fixed butterfly, across the 4 waves in
-// LDS, written as one partial per workgroup and folded by a separate kernel in
-// workgroup order, so every dot product is bitwise reproducible.
+// LDS, written as one partial per workgroup ([column][workgroup], so the fold
+// reads contiguously) and folded by a separate kernel in workgroup order, so
+// every dot product is bitwise reproducible.
 #include <algorithm>
 #include <cstdlib>
 
@@ -129,7 +130,7 @@ __device__ inline void block_reduce_store(double (&red)[NV * VE], int log2G, int
     double s = sred[c];
 #pragma unroll
     for (int wv = 1; wv < kWaves; ++wv) s += sred[wv * w + c];
-    part[(int64_t)blockIdx.x * w + c] = s;
+    part[(int64_t)c * gridDim.x + blockIdx.x] = s;  // [column][workgroup]
   }
 }
 
@@ -389,7 +390,8 @@ __global__ __launch_bounds__(kThreads) void k_pcg_finalize(const double* __restr
   const int c = blockIdx.x * kWaves + wave;
   if (c >= w) return;
   double s = 0.0;
-  for (int g = lane; g < nwg; g += 64) s += part[(int64_t)g * w + c];
+  const double* pc = part + (int64_t)c * nwg;
+  for (int g = lane; g < nwg; g += 64) s += pc[g];
   for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
   if (lane != 0) return;
   PcgCoef& k = coef[col0 + c];
@@ -657,18 +659,82 @@ void run_pcg(const Ham& H, double sigma, const T* jac, const T* R, int64_t ldr, 
       a2.part = part.as<double>();
       const int ntimed = tm ? std::min(m, PcgTiming::kSample) : 0;
       if (tm) tm->init();
-      for (int it = 0; it < m; ++it) {
-        const bool timed = it < ntimed;
-        if (timed) MBL_HIP(hipEventRecord(tm->ev[4 * it + 0], s));
+      auto step = [&]() {
         dispatch_apply<T, EPI_NORM2>(ch, g, a1, s);
-        if (timed) MBL_HIP(hipEventRecord(tm->ev[4 * it + 1], s));
         finalize<FIN_ALPHA>(ch, g, part.as<double>(), cf, s);
-        if (timed) MBL_HIP(hipEventRecord(tm->ev[4 * it + 2], s));
         dispatch_apply<T, EPI_PCG>(ch, g, a2, s);
-        if (timed) MBL_HIP(hipEventRecord(tm->ev[4 * it + 3], s));
+        finalize<FIN_BETA>(ch, g, part.as<double>(), cf, s);
+        dispatch_elt<T, ELT_PUPD>(ch, g, e, s);
+      };
+      int it = 0;
+      for (; it < ntimed; ++it) {
+        MBL_HIP(hipEventRecord(tm->ev[4 * it + 0], s));
+        dispatch_apply<T, EPI_NORM2>(ch, g, a1, s);
+        MBL_HIP(hipEventRecord(tm->ev[4 * it + 1], s));
+        finalize<FIN_ALPHA>(ch, g, part.as<double>(), cf, s);
+        MBL_HIP(hipEventRecord(tm->ev[4 * it + 2], s));
+        dispatch_apply<T, EPI_PCG>(ch, g, a2, s);
+        MBL_HIP(hipEventRecord(tm->ev[4 * it + 3], s));
         finalize<FIN_BETA>(ch, g, part.as<double>(), cf, s);
         dispatch_elt<T, ELT_PUPD>(ch, g, e, s);
       }
+      // The remaining steps replay one captured step: every CG coefficient
+      // lives on the device, so the five launches are identical each step.
+      if (env_int("MBL_PCG_GRAPH", 1) != 0 && m - it >= 8) {
+        // the legacy default stream cannot be captured: fork onto a private
+        // stream (ordered after s by an event) and join back afterwards
+        hipStream_t cs = s, own = nullptr;
+        hipEvent_t fork = nullptr, join = nullptr;
+        if (s == nullptr) {
+          MBL_HIP(hipStreamCreateWithFlags(&own, hipStreamNonBlocking));
+          MBL_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+          MBL_HIP(hipEventCreateWithFlags(&join, hipEventDisableTiming));
+          MBL_HIP(hipEventRecord(fork, s));
+          MBL_HIP(hipStreamWaitEvent(own, fork, 0));
+          cs = own;
+        }
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        hipError_t err = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (err == hipSuccess) {
+          const hipStream_t keep = s;
+          s = cs;  // step() launches on s
+          try {
+            step();
+          } catch (...) {
+            s = keep;
+            hipGraph_t dropped = nullptr;
+            (void)hipStreamEndCapture(cs, &dropped);
+            if (dropped) (void)hipGraphDestroy(dropped);
+            if (own) {
+              (void)hipStreamSynchronize(own);
+              (void)hipStreamDestroy(own);
+              (void)hipEventDestroy(fork);
+              (void)hipEventDestroy(join);
+            }
+            throw;
+          }
+          s = keep;
+          err = hipStreamEndCapture(cs, &graph);
+        }
+        if (err == hipSuccess) err = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        for (; err == hipSuccess && it < m; ++it) err = hipGraphLaunch(exec, cs);
+        if (own && err == hipSuccess) {
+          err = hipEventRecord(join, own);
+          if (err == hipSuccess) err = hipStreamWaitEvent(s, join, 0);
+        }
+        const hipError_t se = hipStreamSynchronize(cs);
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (own) {
+          (void)hipStreamDestroy(own);
+          (void)hipEventDestroy(fork);
+          (void)hipEventDestroy(join);
+        }
+        MBL_HIP(err);
+        MBL_HIP(se);
+      }
+      for (; it < m; ++it) step();
       if (ntimed > 0) {
         MBL_HIP(hipStreamSynchronize(s));
         for (int it = 0; it < ntimed; ++it) {

@@ -110,8 +110,12 @@ struct PhaseBufs {
   }
 };
 
+// CG steps per outer iteration.  The total number of CG steps a solve needs is
+// nearly independent of this split (measured at L = 20: within 10% for m from
+// 125 to 2000); larger m means fewer outer iterations.  40 (n/924)^0.61 gives
+// ~1000 at L = 20 and ~5200 at L = 24 (the paper used 5,000 at L = 24).
 int default_pcg_iters(int64_t n) {
-  const double m = 20.0 * std::pow((double)n / 924.0, 0.61);
+  const double m = 40.0 * std::pow((double)n / 924.0, 0.61);
   return (int)std::max(5.0, std::min(20000.0, std::round(m)));
 }
 

@@ -186,6 +186,22 @@ def test_pcg_column_chunks_agree(dtype, monkeypatch):
     assert not torch.equal(W_full, torch.zeros_like(W_full))
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_pcg_graph_replay_is_bitwise_identical(dtype, monkeypatch):
+    """The captured CG step replayed many times equals direct launches, and the
+    solve's eager work between replays does not disturb it."""
+    L = 14
+    h, H = _ham(L, W=4.0)
+    R = torch.from_numpy(workloads.random_block(H.n, 32, seed=11)).to(DEV, dtype)
+    monkeypatch.setenv("MBL_PCG_GRAPH", "0")
+    W_direct = H.pcg(R, 0.07, 40)
+    monkeypatch.setenv("MBL_PCG_GRAPH", "1")
+    for _ in range(3):
+        W_graph = H.pcg(R, 0.07, 40)
+        assert torch.equal(W_direct, W_graph)
+        _ = (R * 2).sum().item()  # eager work and a synchronisation in between
+
+
 def test_pcg_fp32_close_to_fp64():
     L = 14
     h, H = _ham(L, W=4.0)
