@@ -494,8 +494,11 @@ mbl_status solve_interior(const Ham& H, double sigma, int nev, int b, double tol
       launch_convert<double, float>(n, b, X0.as<double>(), b, x32.as<float>(), b, s);
       ph.init(x32.as<float>(), b);
     }
-    const double sw = std::max(tol, 1e-5);
-    run_phase<float, float>(ph, jac32.as<float>(), p, sw, 4, iters_left, st, theta, res, "fp32");
+    // The inner CG runs in FP32 in both phases, so an FP32-block iteration
+    // costs about as much as an FP64-block one: leave the FP32 phase as soon
+    // as it has done its job (1e-4) or stops making progress.
+    const double sw = std::max(tol, 1e-4);
+    run_phase<float, float>(ph, jac32.as<float>(), p, sw, 3, iters_left, st, theta, res, "fp32");
     launch_convert<float, double>(n, b, ph.X(), ph.ldx(), X0.as<double>(), b, s);
     MBL_HIP(hipStreamSynchronize(s));
   }
