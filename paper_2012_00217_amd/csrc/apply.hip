@@ -24,6 +24,7 @@
 // reads contiguously) and folded by a separate kernel in workgroup order, so
 // every dot product is bitwise reproducible.
 #include <algorithm>
+#include <cmath>
 #include <cstdlib>
 
 #include "common.h"
@@ -421,10 +422,49 @@ int env_int(const char* name, int dflt) {
   return v ? std::atoi(v) : dflt;
 }
 
-// Split columns [0, b) into chunks of at most max_bytes per row.
+// Launch schedule of the apply and CG kernels: bytes of a row chunk, bytes
+// per lane, tiles per XCD group (0 = one group per XCD) and workgroups per XCD.
+struct Sched {
+  int chunk_bytes, lane_bytes, grp, slots;
+};
+
+// Schedules measured best on the MI355X by the package's autotuner, keyed by
+// chain length, sector dimension, bytes per row of the block and element size.
+struct SchedEntry {
+  int L;
+  int64_t n;
+  int row_bytes, elem;
+  Sched s;
+};
+#include "apply_schedules.inc"
+
+constexpr Sched kDefaultSched{512, 64, 0, 256};
+
+// Table entry with the same element size and row width whose sector dimension
+// is closest (within a factor 2.5) to n, else the default; each MBL_APPLY_*
+// environment variable that is set overrides its field.
+Sched sched_for(const Ham& H, int row_bytes, int elem) {
+  Sched best = kDefaultSched;
+  double dist = std::log(2.5);
+  for (const SchedEntry& e : kSchedTable) {
+    if (e.L == 0 || e.elem != elem || e.row_bytes != row_bytes) continue;
+    const double d = std::fabs(std::log((double)e.n / (double)std::max<int64_t>(1, H.n)));
+    if (d <= dist) {
+      dist = d;
+      best = e.s;
+    }
+  }
+  best.chunk_bytes = env_int("MBL_APPLY_CHUNK_BYTES", best.chunk_bytes);
+  best.lane_bytes = env_int("MBL_APPLY_LANE_BYTES", best.lane_bytes);
+  best.grp = env_int("MBL_APPLY_XCD_GROUP", best.grp);
+  best.slots = env_int("MBL_APPLY_SLOTS_PER_XCD", best.slots);
+  return best;
+}
+
+// Split columns [0, b) into chunks of at most sc.chunk_bytes per row.
 template <class T>
-std::vector<Chunk> plan_chunks(int b, bool aligned16) {
-  const int max_bytes = std::max(16, env_int("MBL_APPLY_CHUNK_BYTES", 512));
+std::vector<Chunk> plan_chunks(int b, bool aligned16, const Sched& sc) {
+  const int max_bytes = std::max(16, sc.chunk_bytes);
   std::vector<Chunk> out;
   const int VEv = aligned16 ? (int)(16 / sizeof(T)) : 1;
   int c = 0;
@@ -435,7 +475,7 @@ std::vector<Chunk> plan_chunks(int b, bool aligned16) {
       VE = 1;
       units = b - c;
     }
-    const int lane_units = std::max(1, env_int("MBL_APPLY_LANE_BYTES", 64) / (int)(VE * sizeof(T)));
+    const int lane_units = std::max(1, sc.lane_bytes / (int)(VE * sizeof(T)));
     int NV = 1;
     while (NV * 2 <= std::min(units, std::min(lane_units, VE > 1 ? 8 : 4))) NV *= 2;
     int G = std::min(64, units / NV);
@@ -458,14 +498,14 @@ struct Grid {
   unsigned nwg;
 };
 
-Grid make_grid(int64_t n, int log2G) {
+Grid make_grid(int64_t n, int log2G, const Sched& sc) {
   const int64_t rows_per_tile = kWaves * (64 >> log2G);
   Grid g;
   g.ts.ntiles = (n + rows_per_tile - 1) / rows_per_tile;
   const int64_t per_xcd = (g.ts.ntiles + 7) / 8;
-  const int grp_knob = env_int("MBL_APPLY_XCD_GROUP", 0);
+  const int grp_knob = sc.grp;
   g.ts.grp = (int)std::max<int64_t>(1, grp_knob > 0 ? std::min<int64_t>(grp_knob, per_xcd) : per_xcd);
-  const int64_t max_slots = std::min(256, std::max(1, env_int("MBL_APPLY_SLOTS_PER_XCD", 256)));
+  const int64_t max_slots = std::min(256, std::max(1, sc.slots));
   const int64_t slots = std::min<int64_t>(per_xcd, max_slots);
   g.nwg = (unsigned)(8 * std::max<int64_t>(1, slots));
   return g;
@@ -556,8 +596,9 @@ void launch_apply(const Ham& H, double sigma, const T* X, int64_t ldx, T* Y, int
   a.ldx = ldx;
   a.Y = Y;
   a.ldy = ldy;
-  for (const Chunk& ch : plan_chunks<T>(w, aligned))
-    dispatch_apply<T, EPI_PLAIN>(ch, make_grid(H.n, ch.log2G), a, s);
+  const Sched sc = sched_for(H, w * (int)sizeof(T), (int)sizeof(T));
+  for (const Chunk& ch : plan_chunks<T>(w, aligned, sc))
+    dispatch_apply<T, EPI_PLAIN>(ch, make_grid(H.n, ch.log2G, sc), a, s);
 }
 
 // Block Jacobi-PCG on A = (H - sigma)^2, x0 = 0, m steps, per column:
@@ -620,9 +661,10 @@ void run_pcg(const Ham& H, double sigma, const T* jac, const T* R, int64_t ldr, 
     const int64_t ldx = (wc < b) ? w : ldw;
     PcgCoef* cf = coef + c0;
     const bool aligned = al16(Rc, ldr, sizeof(T)) && al16(x, ldx, sizeof(T)) && al16(r, w, sizeof(T));
-    for (const Chunk& ch : plan_chunks<T>(w, aligned)) {
+    const Sched sc = sched_for(H, w * (int)sizeof(T), (int)sizeof(T));
+    for (const Chunk& ch : plan_chunks<T>(w, aligned, sc)) {
       if ((size_t)ch.w * kMaxWg * sizeof(double) > part.bytes()) fail(MBL_EINTERNAL, "pcg: part");
-      const Grid g = make_grid(n, ch.log2G);
+      const Grid g = make_grid(n, ch.log2G, sc);
       EltArgs<T> e{};
       e.R = Rc;
       e.ldR = ldr;

@@ -170,6 +170,43 @@ def test_pcg_parity(m, b):
         np.testing.assert_allclose(W, Wr, rtol=0, atol=1e-9 * np.abs(Wr).max())
 
 
+# Launch schedules the autotuner may choose: (chunk bytes, lane bytes, tiles per
+# XCD group, workgroups per XCD).  Each must give the same applies (the per-row
+# arithmetic does not depend on the schedule) and oracle-exact CG.
+SCHEDULES = [(128, 16, 4, 128), (256, 32, 16, 256), (256, 64, 64, 64), (512, 64, 1, 3),
+             (128, 32, 0, 256)]
+
+
+def _set_schedule(monkeypatch, sc):
+    for k, v in zip(("MBL_APPLY_CHUNK_BYTES", "MBL_APPLY_LANE_BYTES", "MBL_APPLY_XCD_GROUP",
+                     "MBL_APPLY_SLOTS_PER_XCD"), sc):
+        monkeypatch.setenv(k, str(v))
+
+
+@pytest.mark.parametrize("sc", SCHEDULES)
+@pytest.mark.parametrize("dtype,b", [(torch.float64, 40), (torch.float32, 72)])
+def test_apply_and_pcg_under_every_schedule(sc, dtype, b, monkeypatch):
+    L = 14  # 3432 rows: many tiles and a ragged last tile for every row width
+    h, H = _ham(L, W=4.0)
+    st, Ho = _oracle(L, h)
+    X = workloads.random_block(H.n, b, seed=3)
+    Xd = torch.from_numpy(X).to(DEV, dtype)
+    Xo = X.astype(np.float32).astype(np.float64) if dtype == torch.float32 else X
+    sigma = 0.21
+    ref = H.apply(Xd, sigma)  # default schedule
+    _set_schedule(monkeypatch, sc)
+    Y = H.apply(Xd, sigma)
+    assert torch.equal(Y, ref)
+    tol = 1e-13 if dtype == torch.float64 else 2e-6
+    Yr = hamiltonian.apply_shifted(Ho, Xo, sigma)
+    assert np.all(np.abs(Y.double().cpu().numpy() - Yr) <= tol * _abs_bound(Ho, Xo, sigma) + 1e-30)
+    if dtype == torch.float64:
+        m = 4
+        W = H.pcg(Xd, sigma, m).cpu().numpy()
+        Wr = opcg.pcg_fold(Ho, sigma, hamiltonian.fold_diagonal(Ho, sigma), X, m)
+        np.testing.assert_allclose(W, Wr, rtol=0, atol=1e-9 * np.abs(Wr).max())
+
+
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_pcg_column_chunks_agree(dtype, monkeypatch):
     """Solving the block CG in cache-sized column chunks (ragged last chunk)
