@@ -30,7 +30,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
-APPLY_SRC = os.path.join(ROOT, "paper_2012_00217_amd", "csrc", "apply.hip")
+APPLY_SRC = [os.path.join(ROOT, "paper_2012_00217_amd", "csrc", f)
+             for f in ("apply.hip", "apply_schedules.inc")]
 COUNTERS = os.path.join(ROOT, "profiles", "cg_apply_l20_counters.md")
 
 WORKLOADS = {
@@ -49,8 +50,12 @@ WORKLOADS = {
 
 
 def apply_src_hash():
-    with open(APPLY_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of the apply kernel source and its compiled-in launch schedules."""
+    h = hashlib.sha256()
+    for path in APPLY_SRC:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def read_traffic(kernel):
