@@ -71,7 +71,7 @@ def read_traffic(kernel):
     return float(m.group(1)) if m else None
 
 
-def cpu_baseline(wl, gpu_runs):
+def cpu_baseline(wl, gpu_runs, verbose=False):
     """The FP64 oracle on a bounded sample of the same workload.
 
     Sample: the oracle's step-by-step Jacobi-PCG on the fold of the W=max(Ws)
@@ -85,6 +85,10 @@ def cpu_baseline(wl, gpu_runs):
     from oracle import hamiltonian, linalg, pcg
     from paper_2012_00217_amd import workloads
 
+    def note(msg):
+        if verbose:
+            print(f"[cpu_baseline] {msg}", file=sys.stderr, flush=True)
+
     L, nev, b = wl["L"], wl["nev"], wl["block"]
     W = max(wl["Ws"])
     run = gpu_runs[W]
@@ -93,11 +97,13 @@ def cpu_baseline(wl, gpu_runs):
     st, H = hamiltonian.sector_matrix(L, L // 2, 1.0, 1.0, h)
     d = hamiltonian.fold_diagonal(H, run["sigma"])
     t_setup = time.perf_counter() - t0
+    note(f"sector matrix and fold diagonal: {t_setup:.1f} s")
     R = workloads.random_block(len(st), b, seed=1)
     m = 4
     t0 = time.perf_counter()
     pcg.pcg_fold(H, run["sigma"], d, R, m)
     t_step = (time.perf_counter() - t0) / m
+    note(f"{m} CG steps: {t_step:.2f} s per step")
     t0 = time.perf_counter()
     hamiltonian.apply_shifted(H, R, run["sigma"])
     t_apply = time.perf_counter() - t0
@@ -109,6 +115,7 @@ def cpu_baseline(wl, gpu_runs):
         _, Hw = hamiltonian.sector_matrix(L, L // 2, 1.0, 1.0, hw, states=st)
         res = linalg.residual_norms(Hw, r["evals"], r["evecs"])
         verified[str(w)] = int(np.sum(res <= wl["tol"]))
+        note(f"W={w:g}: {verified[str(w)]} of {len(res)} pairs at residual <= {wl['tol']:g}")
     return {
         "value": nev / t_proj,
         "unit": "eigenpairs/s",
@@ -356,7 +363,7 @@ def main():
         gpu_runs = {W: dict(sigma=sigmas[W], applies=r["info"]["applies"],
                             pcg_steps=r["info"]["pcg_steps"], evals=r["evals"],
                             evecs=r["V"].cpu().numpy()) for W, r in last.items()}
-        cpu = cpu_baseline(wl, gpu_runs)
+        cpu = cpu_baseline(wl, gpu_runs, verbose=args.verbose)
     line = {
         "metric": "eigenpairs/s at resid<=1e-10",
         "value": round(value, 4),

@@ -103,3 +103,33 @@ def matrix_free_apply(L, states, J, Delta, h, X, sigma):
         c = basis.rank(states, states[r] ^ np.uint64(3 << i))
         Y[r] += 0.5 * J * X[c]
     return Y
+
+
+def apply_rows(L, states, J, Delta, h, rows, sigma, fetch):
+    """Rows ``rows`` of H X - sigma X, each from its own definition.
+
+    For a row with state s the result is (E(s) - sigma) X[s] plus J/2 times
+    X at every state reached by one flip-flop of an anti-aligned bond (eq. (1),
+    Sec. 2.1).  ``fetch(idx)`` returns the rows ``idx`` of X as a 2-D array, so
+    X itself may live elsewhere (a device block too large for the host).
+    Returns (Y_rows, bound_rows) with bound = the same sum taken over absolute
+    values, for componentwise rounding tolerances.
+    """
+    rows = np.asarray(rows, dtype=np.int64)
+    s = states[rows]
+    d = diagonal(L, s, J, Delta, h) - sigma
+    Xr = np.asarray(fetch(rows), dtype=np.float64)
+    Y = d[:, None] * Xr
+    B = np.abs(d)[:, None] * np.abs(Xr)
+    for i in range(L - 1):
+        bi = (s >> np.uint64(i)) & np.uint64(1)
+        bj = (s >> np.uint64(i + 1)) & np.uint64(1)
+        k = np.nonzero(bi != bj)[0]
+        if len(k) == 0:
+            continue
+        c = basis.rank(states, s[k] ^ np.uint64(3 << i))
+        assert np.all(c >= 0), "flip left the sector"
+        Xc = np.asarray(fetch(c), dtype=np.float64)
+        Y[k] += 0.5 * J * Xc
+        B[k] += 0.5 * abs(J) * np.abs(Xc)
+    return Y, B

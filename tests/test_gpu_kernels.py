@@ -117,6 +117,32 @@ def test_apply_parity_full_size(L, b):
     assert np.all(np.abs(Y - Yr) <= 1e-13 * _abs_bound(Ho, X, sigma) + 1e-300)
 
 
+@pytest.mark.parametrize("L,b,dtype", [(24, 128, torch.float32), (24, 128, torch.float64),
+                                         (28, 32, torch.float64)])
+def test_apply_sampled_rows_at_full_size(L, b, dtype):
+    """The applies of the L = 24 (block 128, FP32 and FP64) and L = 28 (block 32,
+    FP64) workloads in the launch configuration the solver uses: 600 sampled
+    rows (first, last, tile edges, random) against the oracle's row-wise apply."""
+    h, H = _ham(L, W=4.0)
+    g = torch.Generator(device=DEV)
+    g.manual_seed(L * 1000 + b)
+    X = torch.randn(H.n, b, dtype=dtype, device=DEV, generator=g)
+    sigma = -0.29
+    Y = H.apply(X, sigma)
+    rng = np.random.default_rng(L)
+    edges = np.array([0, 1, 15, 16, 31, 32, 63, 64, 127, 128, H.n - 2, H.n - 1])
+    rows = np.unique(np.concatenate([edges, rng.integers(0, H.n, 588)]))
+    st = basis.enumerate_sector(L, L // 2)
+    assert len(st) == H.n
+    fetch = lambda idx: X[torch.from_numpy(np.asarray(idx)).to(DEV)].double().cpu().numpy()
+    Yr, B = hamiltonian.apply_rows(L, st, 1.0, 1.0, h, rows, sigma, fetch)
+    got = Y[torch.from_numpy(rows).to(DEV)].double().cpu().numpy()
+    tol = 1e-13 if dtype == torch.float64 else 2e-6
+    assert np.all(np.abs(got - Yr) <= tol * B + 1e-300)
+    del X, Y
+    torch.cuda.empty_cache()
+
+
 def test_apply_symmetry_at_l24():
     """<X, H Y> = <H X, Y> at L = 24 (catches rank/index bugs at any size)."""
     L = 24

@@ -80,6 +80,23 @@ def test_delta_zero_free_fermions(L):
     np.testing.assert_allclose(ev, e_ref, atol=1e-10)
 
 
+@pytest.mark.parametrize("precision", ["f64", "mixed"])
+def test_delta_zero_twin_of_the_l20_workload(precision):
+    """The L = 20 workload (n = 184756, 32 pairs, block 64, tol 1e-10) at Delta = 0,
+    where the exact eigenvalues are single-particle subset sums at full size."""
+    L, nev, b = 20, 32, 64
+    h = workloads.disorder(L, 4.0, 0)
+    st = basis.enumerate_sector(L, L // 2)
+    e_all = freefermion.energies(L, L // 2, 1.0, h, st)
+    sigma = spectrum.shift_from_density(e_all.min(), e_all.max(), 0.5)
+    e_ref, _ = freefermion.nearest(L, L // 2, 1.0, h, st, sigma, nev)
+    H = api.Hamiltonian(L, h, Delta=0.0)
+    ev, V, rs, info = H.solve(sigma, nev, b, tol=1e-10, precision=precision)
+    _, Ho = hamiltonian.sector_matrix(L, L // 2, 1.0, 0.0, h, states=st)
+    assert np.all(linalg.residual_norms(Ho, ev, V.cpu().numpy()) <= 1e-10)
+    np.testing.assert_allclose(ev, e_ref, atol=1e-10)
+
+
 def test_solve_is_deterministic():
     L = 12
     h = workloads.disorder(L, 4.0, 2)

@@ -158,6 +158,21 @@ def test_apply_paths_agree_with_dense():
     np.testing.assert_allclose(hamiltonian.apply_fold(H, X, sigma), A @ X, atol=1e-10)
 
 
+def test_row_wise_apply_matches_dense_rows_and_bound():
+    """apply_rows on scattered rows (fetching X through a callback) equals the
+    dense rows of H X - sigma X, and its bound is |H - sigma I| |X| row by row."""
+    L, k = 12, 5
+    h = np.random.default_rng(8).uniform(-3, 3, L)
+    J, Delta, sigma = 0.7, 1.3, -0.4
+    st, H = hamiltonian.sector_matrix(L, k, J, Delta, h)
+    X = np.random.default_rng(9).standard_normal((len(st), 5))
+    rows = np.array([0, 3, 17, 400, len(st) - 1])
+    Y, B = hamiltonian.apply_rows(L, st, J, Delta, h, rows, sigma, lambda idx: X[idx])
+    Hd = H.toarray() - sigma * np.eye(len(st))
+    np.testing.assert_allclose(Y, (Hd @ X)[rows], atol=1e-12)
+    np.testing.assert_allclose(B, (np.abs(Hd) @ np.abs(X))[rows], atol=1e-12)
+
+
 def test_fold_diagonal_matches_dense_square_and_closed_form():
     """diag((H - sigma)^2) = (E - sigma)^2 + (J/2)^2 * (number of active bonds)."""
     L, k, J, sigma = 10, 5, 1.0, -0.8
