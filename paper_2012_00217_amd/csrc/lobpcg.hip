@@ -418,12 +418,13 @@ double maxv(const std::vector<double>& v) {
 }
 
 // Runs LOBPCG iterations of one phase until the wanted residuals are below
-// stop_tol, stagnation (no 10% progress in `patience` steps, if patience > 0)
-// or the iteration budget is used.  Returns true on reaching stop_tol.
+// stop_tol, stagnation (if patience > 0: `patience` steps in a row that do not
+// bring the largest residual below gain times the best so far) or the
+// iteration budget is used.  Returns true on reaching stop_tol.
 template <class TB, class TP>
 bool run_phase(Phase<TB>& ph, const TP* jac, const Params& p, double stop_tol, int patience,
-               int& iters_left, Stats& st, std::vector<double>& theta, std::vector<double>& res,
-               const char* tag) {
+               double gain, int& iters_left, Stats& st, std::vector<double>& theta,
+               std::vector<double>& res, const char* tag) {
   const int m = p.pcg_iters;
   double best = INFINITY;
   int since = 0;
@@ -435,7 +436,7 @@ bool run_phase(Phase<TB>& ph, const TP* jac, const Params& p, double stop_tol, i
                    (long long)st.applies, r);
     if (r <= stop_tol) return true;
     if (patience > 0) {
-      if (r < 0.9 * best) {
+      if (r < gain * best) {
         best = r;
         since = 0;
       } else if (++since >= patience) {
@@ -495,10 +496,13 @@ mbl_status solve_interior(const Ham& H, double sigma, int nev, int b, double tol
       ph.init(x32.as<float>(), b);
     }
     // The inner CG runs in FP32 in both phases, so an FP32-block iteration
-    // costs about as much as an FP64-block one: leave the FP32 phase as soon
-    // as it has done its job (1e-4) or stops making progress.
+    // costs about as much as an FP64-block one, and the FP64-block phase
+    // reduces the residual about twofold per iteration down to the tolerance.
+    // Leave the FP32 phase at 1e-4 or at the first iteration that does not
+    // halve the residual, whichever comes first.
     const double sw = std::max(tol, 1e-4);
-    run_phase<float, float>(ph, jac32.as<float>(), p, sw, 3, iters_left, st, theta, res, "fp32");
+    run_phase<float, float>(ph, jac32.as<float>(), p, sw, 1, 0.5, iters_left, st, theta, res,
+                            "fp32");
     launch_convert<float, double>(n, b, ph.X(), ph.ldx(), X0.as<double>(), b, s);
     MBL_HIP(hipStreamSynchronize(s));
   }
@@ -510,10 +514,10 @@ mbl_status solve_interior(const Ham& H, double sigma, int nev, int b, double tol
     while (true) {
       bool reached;
       if (prec == MBL_F64)
-        reached = run_phase<double, double>(ph, jac64.as<double>(), p, tol, 0, iters_left, st,
+        reached = run_phase<double, double>(ph, jac64.as<double>(), p, tol, 0, 0.0, iters_left, st,
                                             theta, res, "fp64");
       else
-        reached = run_phase<double, float>(ph, jac32.as<float>(), p, tol, 0, iters_left, st, theta,
+        reached = run_phase<double, float>(ph, jac32.as<float>(), p, tol, 0, 0.0, iters_left, st, theta,
                                            res, "fp64/pcg32");
       ph.vectors(V.as<double>(), nev);
       res = fresh_residuals(H, sigma, V.as<double>(), nev, nev, theta, st, s);
@@ -614,7 +618,7 @@ mbl_status spectrum_bounds(const Ham& H, double tol, double* emin, double* emax,
     int left = 5000;
     // residual r bounds the eigenvalue error by r^2 / gap for an extreme pair
     const double rtol = std::max(1e-9, std::sqrt(tol) * 1e-2);
-    run_phase<double, double>(ph, (const double*)nullptr, p, rtol, 0, left, st, theta, res,
+    run_phase<double, double>(ph, (const double*)nullptr, p, rtol, 0, 0.0, left, st, theta, res,
                               "bounds");
     out[k] = p.sign * theta[0];
   }
