@@ -306,7 +306,7 @@ def test_combine_parity(n, p, q, dtype):
     assert np.all(np.abs(Y - want) <= tol * (np.abs(Ar) @ np.abs(Cr)) + 1e-300)
 
 
-@pytest.mark.parametrize("m", [1, 2, 7, 48, 96, 97, 192, 384])
+@pytest.mark.parametrize("m", [1, 2, 3, 7, 33, 48, 95, 96, 97, 192, 384])
 def test_small_eigh(m):
     rng = np.random.default_rng(m)
     A = rng.standard_normal((m, m))
