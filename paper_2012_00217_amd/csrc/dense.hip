@@ -65,6 +65,9 @@ __device__ inline void rot_block(double ck, double sk, double cl, double sl, dou
 }
 
 // Whole Jacobi eigensolver in one workgroup; A, V in LDS (mm even, mm <= 96).
+// The pairs of a round are tabulated once per round, and every thread keeps a
+// fixed pair column l (and walks rows k, or matrix rows i, with a fixed stride),
+// so the inner loops do no integer division.
 __global__ __launch_bounds__(1024) void k_jacobi_lds(int m, const double* __restrict__ A,
                                                      int64_t lda, double* __restrict__ w,
                                                      double* __restrict__ V, int64_t ldv,
@@ -73,12 +76,13 @@ __global__ __launch_bounds__(1024) void k_jacobi_lds(int m, const double* __rest
   const int mm = m + (m & 1);
   double* a = sh;             // mm x mm
   double* v = sh + mm * mm;   // mm x mm
-  __shared__ double cs_c[512], cs_s[512];
+  __shared__ double cs_c[48], cs_s[48];
+  __shared__ int pp[48], qq[48];
   __shared__ int nrot;
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int e = tid; e < mm * mm; e += nt) {
     const int i = e / mm, j = e % mm;
-    a[e] = (i < m && j < m) ? A[(int64_t)i * lda + j] : (i == j ? 0.0 : 0.0);
+    a[e] = (i < m && j < m) ? A[(int64_t)i * lda + j] : 0.0;
     v[e] = (i == j) ? 1.0 : 0.0;
   }
   // symmetrise from the upper triangle
@@ -89,43 +93,46 @@ __global__ __launch_bounds__(1024) void k_jacobi_lds(int m, const double* __rest
   }
   __syncthreads();
   const int np = mm / 2;
+  const int rows_per_pass = nt / np;          // threads sharing one pair column
+  const int l = tid % np, r0 = tid / np;      // this thread's column and first row
+  const bool worker = r0 < rows_per_pass;     // the last nt % np threads idle
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     if (tid == 0) nrot = 0;
     __syncthreads();
     for (int round = 0; round < mm - 1; ++round) {
-      for (int k = tid; k < np; k += nt) {
+      if (tid < np) {
         int p, q;
-        pair_of(mm, round, k, &p, &q);
+        pair_of(mm, round, tid, &p, &q);
         double c, s;
         if (rotation(a[p * mm + p], a[q * mm + q], a[p * mm + q], &c, &s)) atomicAdd(&nrot, 1);
-        cs_c[k] = c;
-        cs_s[k] = s;
+        cs_c[tid] = c;
+        cs_s[tid] = s;
+        pp[tid] = p;
+        qq[tid] = q;
       }
       __syncthreads();
-      for (int e = tid; e < np * np; e += nt) {
-        const int k = e / np, l = e % np;
-        int pk, qk, pl, ql;
-        pair_of(mm, round, k, &pk, &qk);
-        pair_of(mm, round, l, &pl, &ql);
-        double bpp = a[pk * mm + pl], bpq = a[pk * mm + ql], bqp = a[qk * mm + pl],
-               bqq = a[qk * mm + ql];
-        rot_block(cs_c[k], cs_s[k], cs_c[l], cs_s[l], bpp, bpq, bqp, bqq);
-        if (k == l) {
-          bpq = 0.0;
-          bqp = 0.0;
+      if (worker) {
+        const int pl = pp[l], ql = qq[l];
+        const double cl = cs_c[l], sl = cs_s[l];
+        for (int k = r0; k < np; k += rows_per_pass) {
+          const int pk = pp[k], qk = qq[k];
+          double bpp = a[pk * mm + pl], bpq = a[pk * mm + ql], bqp = a[qk * mm + pl],
+                 bqq = a[qk * mm + ql];
+          rot_block(cs_c[k], cs_s[k], cl, sl, bpp, bpq, bqp, bqq);
+          if (k == l) {
+            bpq = 0.0;
+            bqp = 0.0;
+          }
+          a[pk * mm + pl] = bpp;
+          a[pk * mm + ql] = bpq;
+          a[qk * mm + pl] = bqp;
+          a[qk * mm + ql] = bqq;
         }
-        a[pk * mm + pl] = bpp;
-        a[pk * mm + ql] = bpq;
-        a[qk * mm + pl] = bqp;
-        a[qk * mm + ql] = bqq;
-      }
-      for (int e = tid; e < mm * np; e += nt) {
-        const int i = e / np, l = e % np;
-        int pl, ql;
-        pair_of(mm, round, l, &pl, &ql);
-        const double vp = v[i * mm + pl], vq = v[i * mm + ql];
-        v[i * mm + pl] = cs_c[l] * vp - cs_s[l] * vq;
-        v[i * mm + ql] = cs_s[l] * vp + cs_c[l] * vq;
+        for (int i = r0; i < mm; i += rows_per_pass) {
+          const double vp = v[i * mm + pl], vq = v[i * mm + ql];
+          v[i * mm + pl] = cl * vp - sl * vq;
+          v[i * mm + ql] = sl * vp + cl * vq;
+        }
       }
       __syncthreads();
     }
