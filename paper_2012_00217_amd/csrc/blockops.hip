@@ -186,6 +186,22 @@ __global__ __launch_bounds__(256) void k_convert(int64_t n, int b, const S* __re
   Y[r * ldy + c] = (D)X[r * ldx + c];
 }
 
+// Diagonal preconditioner of the extreme-eigenvalue iteration (sign*H):
+// W[r,c] = R[r,c] / max(|sign*E_r - mu_c|, floor), with E the diagonal of H and
+// mu the current Ritz values.
+__global__ __launch_bounds__(256) void k_diag_precond(int64_t n, int b, const double* __restrict__ R,
+                                                      int64_t ldr, const double* __restrict__ E,
+                                                      double sign, const double* __restrict__ mu,
+                                                      double floor, double* __restrict__ W,
+                                                      int64_t ldw) {
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= n * b) return;
+  const int64_t r = idx / b;
+  const int c = (int)(idx % b);
+  const double d = fmax(fabs(sign * E[r] - mu[c]), floor);
+  W[r * ldw + c] = R[r * ldr + c] / d;
+}
+
 // splitmix64 (Steele, Lea, Flood 2014) of a counter, then Box-Muller.
 __device__ inline uint64_t splitmix64(uint64_t z) {
   z += 0x9e3779b97f4a7c15ull;
@@ -246,6 +262,15 @@ template <class S, class D>
 void launch_convert(int64_t n, int b, const S* X, int64_t ldx, D* Y, int64_t ldy, hipStream_t s) {
   if (n * b == 0) return;
   hipLaunchKernelGGL((k_convert<S, D>), dim3(g1(n * b)), dim3(256), 0, s, n, b, X, ldx, Y, ldy);
+  MBL_CHECK_LAUNCH();
+}
+
+void launch_diag_precond(int64_t n, int b, const double* R, int64_t ldr, const double* E,
+                         double sign, const double* mu, double floor, double* W, int64_t ldw,
+                         hipStream_t s) {
+  if (n * b == 0) return;
+  hipLaunchKernelGGL(k_diag_precond, dim3(g1(n * b)), dim3(256), 0, s, n, b, R, ldr, E, sign, mu,
+                     floor, W, ldw);
   MBL_CHECK_LAUNCH();
 }
 

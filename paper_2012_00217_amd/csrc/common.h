@@ -158,6 +158,9 @@ size_t small_eigh_work_bytes(int m);
 
 template <class S, class D>
 void launch_convert(int64_t n, int b, const S* X, int64_t ldx, D* Y, int64_t ldy, hipStream_t s);
+void launch_diag_precond(int64_t n, int b, const double* R, int64_t ldr, const double* E,
+                         double sign, const double* mu, double floor, double* W, int64_t ldw,
+                         hipStream_t s);
 template <class T>
 void launch_randn(int64_t n, int b, uint64_t seed, T* X, int64_t ldx, hipStream_t s);
 

@@ -58,6 +58,7 @@ struct Params {
   uint64_t seed = 0;
   bool fold = true;   // false: plain LOBPCG on sign * (H - sigma)
   double sign = 1.0;
+  bool diag_precond = false;  // plain mode: W = R / |sign*diag(H) - mu| instead of W = R
 };
 
 struct Stats {
@@ -337,6 +338,16 @@ class Phase {
       st_.applies += 2LL * m;
       st_.pcg_steps += m;
       st_.t_pcg += secs(t0);
+    } else if constexpr (std::is_same<TB, double>::value) {
+      if (!p_.fold && p_.diag_precond) {
+        // Davidson-type diagonal preconditioner; the floor J/2 is the size of
+        // one flip-flop element, below which the diagonal says nothing
+        const double floor = std::max(0.5 * std::fabs(H_.J), 1e-6);
+        launch_diag_precond(n, b, R, b, H_.diag.as<double>(), p_.sign, sm_.w.as<double>(), floor,
+                            W, ld, s_);
+      } else {
+        copy_cols<TB>(n, b, R, b, W, ld, s_);
+      }
     } else {
       copy_cols<TB>(n, b, R, b, W, ld, s_);
     }
@@ -605,6 +616,7 @@ mbl_status spectrum_bounds(const Ham& H, double tol, double* emin, double* emax,
     Params p;
     p.fold = false;
     p.sign = k == 0 ? 1.0 : -1.0;
+    p.diag_precond = true;
     p.b = b;
     p.nev = 1;
     p.seed = 12345 + k;
