@@ -424,21 +424,28 @@ __global__ __launch_bounds__(kThreads) void k_pcg_elt(EltArgs<T> a) {
 }
 
 // Fold the per-workgroup partials of one chunk (fixed order) and update the
-// CG coefficients of its columns.  One wavefront per column.
+// CG coefficients of its columns.  One workgroup per column: each thread sums
+// a fixed strided subset, then the wavefronts (butterfly) and the workgroup
+// (LDS, wave order) combine them.
 enum { FIN_INIT = 0, FIN_ALPHA = 1, FIN_BETA = 2 };
 
 template <int MODE>
 __global__ __launch_bounds__(kThreads) void k_pcg_finalize(const double* __restrict__ part,
                                                            int nwg, int w, int col0,
                                                            PcgCoef* __restrict__ coef) {
+  __shared__ double swave[kWaves];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int c = blockIdx.x * kWaves + wave;
-  if (c >= w) return;
+  const int c = blockIdx.x;
+  if (c >= w) return;  // uniform over the workgroup
   double s = 0.0;
   const double* pc = part + (int64_t)c * nwg;
-  for (int g = lane; g < nwg; g += 64) s += pc[g];
+  for (int g = threadIdx.x; g < nwg; g += kThreads) s += pc[g];
   for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
-  if (lane != 0) return;
+  if (lane == 0) swave[wave] = s;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  s = swave[0];
+  for (int v = 1; v < kWaves; ++v) s += swave[v];
   PcgCoef& k = coef[col0 + c];
   if (MODE == FIN_INIT) {
     k.rho = s;
@@ -610,7 +617,7 @@ void dispatch_elt(const Chunk& ch, const Grid& g, EltArgs<T> a, hipStream_t s) {
 
 template <int MODE>
 void finalize(const Chunk& ch, const Grid& g, const double* part, PcgCoef* coef, hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_finalize<MODE>, dim3((ch.w + kWaves - 1) / kWaves), dim3(kThreads), 0,
+  hipLaunchKernelGGL(k_pcg_finalize<MODE>, dim3(ch.w), dim3(kThreads), 0,
                      s, part, (int)g.nwg, ch.w, ch.col0, coef);
   MBL_CHECK_LAUNCH();
 }
