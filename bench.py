@@ -220,12 +220,60 @@ def run_serve(args):
     print(json.dumps(out), flush=True)
 
 
+def run_gram(args):
+    """The MFMA Gram kernel alone on the Rayleigh-Ritz shapes of the solves:
+    C = S^T S for S of n rows and m = 3 x block columns.  Flops 2 n m^2 (the
+    kernel forms the full product); TFLOP/s against the dtype's MFMA peak."""
+    import torch
+    from paper_2012_00217_amd import api
+
+    shapes = [("L=20 Rayleigh-Ritz (block 64), FP64", 184756, 192, torch.float64),
+              ("L=24 Rayleigh-Ritz (block 128), FP32", 2704156, 384, torch.float32),
+              ("L=24 Rayleigh-Ritz (block 128), FP64", 2704156, 384, torch.float64),
+              ("batch L=18 Rayleigh-Ritz (block 32), FP64", 48620, 96, torch.float64)]
+    torch.cuda.init()
+    res = []
+    for name, n, m, dt in shapes:
+        g = torch.Generator(device="cuda")
+        g.manual_seed(n + m)
+        S = torch.randn(n, m, dtype=dt, device="cuda", generator=g)
+        for _ in range(2):
+            api.gram(S, S)
+        torch.cuda.synchronize()
+        reps = 20
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            api.gram(S, S)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        tf = 2.0 * n * m * m / (ms * 1e-3) / 1e12
+        peak = 157.3 if dt == torch.float32 else 78.6  # dense MFMA peaks of the MI355X
+        res.append({"shape": name, "n": n, "m": m, "ms": round(ms, 4), "tflops": round(tf, 2),
+                    "peak_tflops": peak, "frac": round(tf / peak, 4)})
+        del S
+        torch.cuda.empty_cache()
+    top = max(res, key=lambda r: r["ms"])
+    out = {"metric": "Gram TFLOP/s (MFMA)", "value": top["tflops"], "unit": "TFLOP/s", "n_gpus": 1,
+           "steps": 20, "warmup": 2, "ms_per_step": top["ms"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32" if "FP32" in top["shape"] else "f64", "data": "synthetic",
+           "config": {"workload": "Gram C = S^T S of the solvers' Rayleigh-Ritz blocks"},
+           "roofline": {"bound": "mfma", "achieved": top["tflops"], "peak": top["peak_tflops"],
+                        "unit": "TFLOP/s", "frac": top["frac"], "traffic": None},
+           "shapes": res}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=0)
-    ap.add_argument("--workload", default="l20", choices=sorted(WORKLOADS) + ["batch", "serve"])
+    ap.add_argument("--workload", default="l20",
+                    choices=sorted(WORKLOADS) + ["batch", "serve", "gram"])
     ap.add_argument("--count", type=int, default=256, help="batch/serve: number of problems")
     ap.add_argument("--concurrency", type=int, default=8, help="batch/serve: concurrent solves")
     ap.add_argument("--plain", action="store_true", help="batch: also solve one at a time")
@@ -245,6 +293,8 @@ def main():
 
     if args.workload == "batch":
         return run_batch(args)
+    if args.workload == "gram":
+        return run_gram(args)
     if args.workload == "serve":
         return run_serve(args)
 

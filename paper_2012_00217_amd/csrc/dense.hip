@@ -224,18 +224,29 @@ __global__ __launch_bounds__(256) void k_jacobi_sort(int m, int mm, const double
 
 // Cholesky with dropping (row-oriented) and inverse of R on the kept columns.
 // G: b x b (upper triangle read).  Outputs Rinv_c (b x b, ld b; column jc is
-// the jc-th kept column of R^-1, other columns zero) and *count.
+// the jc-th kept column of R^-1, other columns zero) and *count.  R and R^-1
+// live in LDS when in_lds (b <= kCholLds), else in global memory (R in the
+// work buffer).  R^-1 is built one row at a time from the bottom, every
+// thread owning columns, so each step is parallel over the columns.
+constexpr int kCholLds = 88;  // 2 b^2 doubles + the static arrays fit 160 KB of LDS
+
 __global__ __launch_bounds__(1024) void k_chol_drop(int b, const double* __restrict__ G,
-                                                    int64_t ldg, double tol,
-                                                    double* __restrict__ R,
+                                                    int64_t ldg, double tol, int in_lds,
+                                                    double* __restrict__ Rg,
                                                     double* __restrict__ Rinv,
                                                     int* __restrict__ count) {
+  extern __shared__ double shm[];
   __shared__ int keep[1024];
   __shared__ int pos[1024];
   __shared__ double row[1024];
   __shared__ double rjj;
   const int tid = threadIdx.x, nt = blockDim.x;
-  for (int e = tid; e < b * b; e += nt) R[e] = 0.0;
+  double* R = in_lds ? shm : Rg;
+  double* Ri = in_lds ? shm + b * b : Rinv;
+  for (int e = tid; e < b * b; e += nt) {
+    R[e] = 0.0;
+    Ri[e] = 0.0;
+  }
   __syncthreads();
   for (int j = 0; j < b; ++j) {
     for (int l = j + tid; l < b; l += nt) {
@@ -265,21 +276,27 @@ __global__ __launch_bounds__(1024) void k_chol_drop(int b, const double* __restr
     *count = c;
   }
   __syncthreads();
-  for (int e = tid; e < b * b; e += nt) Rinv[e] = 0.0;
-  __syncthreads();
-  // column j of R^-1 by back substitution over kept indices
-  for (int j = tid; j < b; j += nt) {
-    if (!keep[j]) continue;
-    const int jc = pos[j];
-    Rinv[j * b + jc] = 1.0 / R[j * b + j];
-    for (int i = j - 1; i >= 0; --i) {
-      if (!keep[i]) continue;
-      double s = 0.0;
-      for (int k = i + 1; k <= j; ++k)
-        if (keep[k]) s += R[i * b + k] * Rinv[k * b + jc];
-      Rinv[i * b + jc] = -s / R[i * b + i];
+  // row i of R^-1 (kept columns only) from the rows below it
+  for (int i = b - 1; i >= 0; --i) {
+    if (keep[i]) {
+      const double rii = R[i * b + i];
+      for (int j = i + tid; j < b; j += nt) {
+        if (!keep[j]) continue;
+        const int jc = pos[j];
+        if (j == i) {
+          Ri[i * b + jc] = 1.0 / rii;
+          continue;
+        }
+        double s = 0.0;
+        for (int k = i + 1; k <= j; ++k)
+          if (keep[k]) s += R[i * b + k] * Ri[k * b + jc];
+        Ri[i * b + jc] = -s / rii;
+      }
     }
+    __syncthreads();
   }
+  if (in_lds)
+    for (int e = tid; e < b * b; e += nt) Rinv[e] = Ri[e];
 }
 
 // C = alpha op(A) op(B) + beta C for small row-major FP64 matrices.
@@ -400,7 +417,13 @@ int chol_drop(int b, const double* G, int64_t ldg, double tol, double* Rinv, dou
               int* dcount, hipStream_t s) {
   if (b <= 0) return 0;
   if (b > 1024) fail(MBL_EINVAL, "chol_drop: b > 1024");
-  hipLaunchKernelGGL(k_chol_drop, dim3(1), dim3(1024), 0, s, b, G, ldg, tol, work, Rinv, dcount);
+  const int in_lds = b <= kCholLds;
+  const size_t shm = in_lds ? (size_t)2 * b * b * sizeof(double) : 0;
+  if (in_lds)
+    MBL_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_chol_drop),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+  hipLaunchKernelGGL(k_chol_drop, dim3(1), dim3(1024), shm, s, b, G, ldg, tol, in_lds, work, Rinv,
+                     dcount);
   MBL_CHECK_LAUNCH();
   int c = 0;
   MBL_HIP(hipMemcpyAsync(&c, dcount, sizeof(int), hipMemcpyDeviceToHost, s));
