@@ -47,15 +47,30 @@ struct Mfma<float> {
 // it receives D[Mfma<T>::row(l / 16, v)][l % 16], v = 0..3.  For C = A^T B the MFMA A
 // operand is the transpose of the block, so both operands read 4 rows x 16
 // consecutive columns of the row-major blocks.
+// sym (A = B, p = q): only the tiles on and above the diagonal are formed;
+// blockIdx.x enumerates them row by row.
 template <class T>
 __global__ __launch_bounds__(256) void k_gram(int64_t n, const T* __restrict__ A, int64_t lda,
                                               int p, const T* __restrict__ B, int64_t ldb, int q,
-                                              int64_t rows_per_split, double* __restrict__ part) {
+                                              int sym, int64_t rows_per_split,
+                                              double* __restrict__ part) {
   using M = Mfma<T>;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wy = wave >> 1, wx = wave & 1;
   const int tiles_q = (q + 63) / 64;
-  const int ty = blockIdx.x / tiles_q, tx = blockIdx.x % tiles_q;
+  int ty, tx;
+  if (sym) {
+    int t = blockIdx.x;
+    ty = 0;
+    while (t >= tiles_q - ty) {
+      t -= tiles_q - ty;
+      ++ty;
+    }
+    tx = ty + t;
+  } else {
+    ty = blockIdx.x / tiles_q;
+    tx = blockIdx.x % tiles_q;
+  }
   const int c0 = ty * 64 + wy * 32, d0 = tx * 64 + wx * 32;
   const int li = lane & 15, lk = lane >> 4;
   const int64_t kb = (int64_t)blockIdx.y * rows_per_split;
@@ -74,8 +89,9 @@ __global__ __launch_bounds__(256) void k_gram(int64_t n, const T* __restrict__ A
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = typename M::acc{0, 0, 0, 0};
-  for (int64_t k = kb; k < ke; k += 16) {
-    T a[4][2], b[4][2];
+  // operands of 16 rows per step; the next step's are loaded before this
+  // step's MFMAs issue, so the loads overlap the matrix-core work
+  auto load = [&](int64_t k, T (&a)[4][2], T (&b)[4][2]) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int64_t row = k + 4 * u + lk;
@@ -86,12 +102,25 @@ __global__ __launch_bounds__(256) void k_gram(int64_t n, const T* __restrict__ A
         b[u][v] = (ok && okb[v]) ? B[row * ldb + cb[v]] : (T)0;
       }
     }
+  };
+  T a[4][2], b[4][2];
+  if (kb < ke) load(kb, a, b);
+  for (int64_t k = kb; k < ke; k += 16) {
+    T an[4][2], bn[4][2];
+    load(k + 16, an, bn);  // rows at or past ke load as zeros
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = M::op(a[u][i], b[u][j], acc[i][j]);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 2; ++v) {
+        a[u][v] = an[u][v];
+        b[u][v] = bn[u][v];
+      }
   }
   double* out = part + (int64_t)blockIdx.y * p * q;
 #pragma unroll
@@ -108,14 +137,17 @@ __global__ __launch_bounds__(256) void k_gram(int64_t n, const T* __restrict__ A
 
 // One wavefront per output element: lane l sums splits l, l+64, ... in order,
 // then a fixed butterfly folds the 64 lane sums.
+// sym: elements of tiles below the diagonal are read from their mirror.
 __global__ __launch_bounds__(256) void k_gram_fold(const double* __restrict__ part, int splits,
-                                                   int p, int q, double* __restrict__ C,
+                                                   int p, int q, int sym, double* __restrict__ C,
                                                    int64_t ldc) {
   const int lane = threadIdx.x & 63;
   const int64_t idx = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (idx >= (int64_t)p * q) return;
+  const int r = (int)(idx / q), c = (int)(idx % q);
+  const int64_t src = (sym && (r >> 6) > (c >> 6)) ? (int64_t)c * q + r : idx;
   double s = 0.0;
-  for (int sp = lane; sp < splits; sp += 64) s += part[(int64_t)sp * p * q + idx];
+  for (int sp = lane; sp < splits; sp += 64) s += part[(int64_t)sp * p * q + src];
   for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
   if (lane == 0) C[(idx / q) * ldc + idx % q] = s;
 }
@@ -230,7 +262,10 @@ template <class T>
 void launch_gram(int64_t n, const T* A, int64_t lda, int p, const T* B, int64_t ldb, int q,
                  double* C, int64_t ldc, hipStream_t s) {
   if (p == 0 || q == 0) return;
-  const int tiles = ((p + 63) / 64) * ((q + 63) / 64);
+  // A^T A: only the upper tiles (the Rayleigh-Ritz and Cholesky-QR Grams)
+  const int sym = (A == B && lda == ldb && p == q) ? 1 : 0;
+  const int tq = (q + 63) / 64;
+  const int tiles = sym ? tq * (tq + 1) / 2 : ((p + 63) / 64) * tq;
   int64_t splits = std::max<int64_t>(1, 1024 / tiles);
   splits = std::min<int64_t>(splits, std::max<int64_t>(1, (n + 255) / 256));
   int64_t rows = (n + splits - 1) / splits;
@@ -239,13 +274,13 @@ void launch_gram(int64_t n, const T* A, int64_t lda, int p, const T* B, int64_t 
   DevBuf part((size_t)splits * p * q * sizeof(double), s);
   if (n > 0) {
     hipLaunchKernelGGL(k_gram<T>, dim3(tiles, (unsigned)splits), dim3(256), 0, s, n, A, lda, p, B,
-                       ldb, q, rows, part.as<double>());
+                       ldb, q, sym, rows, part.as<double>());
     MBL_CHECK_LAUNCH();
   } else {
     MBL_HIP(hipMemsetAsync(part.get(), 0, part.bytes(), s));
   }
   hipLaunchKernelGGL(k_gram_fold, dim3((unsigned)(((int64_t)p * q + 3) / 4)), dim3(256), 0, s,
-                     part.as<double>(), (int)splits, p, q, C, ldc);
+                     part.as<double>(), (int)splits, p, q, sym, C, ldc);
   MBL_CHECK_LAUNCH();
 }
 

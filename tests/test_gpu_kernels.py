@@ -292,6 +292,22 @@ def test_gram_parity(n, p, q, dtype):
     assert np.array_equal(G, G2)  # fixed-order reduction: bitwise repeatable
 
 
+@pytest.mark.parametrize("n,m", [(1000, 48), (777, 17), (20000, 192), (5003, 130), (65, 64)])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_gram_symmetric_path(n, m, dtype):
+    """A^T A forms only the tiles on and above the diagonal and mirrors the rest."""
+    A = workloads.random_block(n, m, seed=5)
+    At = torch.from_numpy(A).to(DEV, dtype)
+    G = api.gram(At, At).cpu().numpy()
+    Ar = At.double().cpu().numpy()
+    tol = 1e-13 if dtype == torch.float64 else 1e-5
+    assert np.all(np.abs(G - Ar.T @ Ar) <= tol * (np.abs(Ar).T @ np.abs(Ar)) + 1e-300)
+    assert np.array_equal(G, G.T)
+    # the general path on a copy (different pointer) agrees to rounding
+    G2 = api.gram(At, At.clone()).cpu().numpy()
+    assert np.all(np.abs(G - G2) <= 2 * tol * (np.abs(Ar).T @ np.abs(Ar)) + 1e-300)
+
+
 @pytest.mark.parametrize("n,p,q", [(1000, 48, 16), (777, 17, 5), (20000, 192, 64)])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_combine_parity(n, p, q, dtype):
