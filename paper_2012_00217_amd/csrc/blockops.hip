@@ -45,16 +45,67 @@ struct Mfma<float> {
 // 32 x 32 quadrant as 2 x 2 blocks of 16 x 16.  16 x 16 x 4 MFMA operand
 // layout: lane l supplies A[i = l % 16][k = l / 16] and B[k = l / 16][j = l % 16];
 // it receives D[Mfma<T>::row(l / 16, v)][l % 16], v = 0..3.  For C = A^T B the MFMA A
-// operand is the transpose of the block, so both operands read 4 rows x 16
+// operand is the transpose of the block, so both operands are 4 rows x 16
 // consecutive columns of the row-major blocks.
+//
+// The rows are consumed in slabs of 32: the workgroup stages the slab's
+// 32 x 64 panels of A and B in LDS (16-byte loads when the blocks are aligned,
+// each element read from memory once per workgroup), and the next slab's
+// loads are in flight while the waves run their 32 MFMAs on the current one.
 // sym (A = B, p = q): only the tiles on and above the diagonal are formed;
-// blockIdx.x enumerates them row by row.
+// blockIdx.x enumerates them row by row, and a diagonal tile stages one panel.
+constexpr int kSlab = 32;
+
+template <class T>
+struct GramStage {
+  static constexpr int VE = 16 / (int)sizeof(T);           // elements per 16-byte load
+  static constexpr int PER = kSlab * 64 / (256 * VE);       // loads per thread per panel
+  static constexpr int LD = 64 + VE;                        // padded LDS row
+};
+
+template <class T>
+__device__ inline void gram_load(const T* __restrict__ X, int64_t ldx, int ncol, int col0,
+                                 int64_t k, int64_t ke, bool vec, T (&reg)[GramStage<T>::PER][GramStage<T>::VE]) {
+  using S = GramStage<T>;
+#pragma unroll
+  for (int u = 0; u < S::PER; ++u) {
+    const int e = (u * 256 + (int)threadIdx.x) * S::VE;  // element in the 32 x 64 panel
+    const int r = e >> 6, c = e & 63;
+    const int64_t row = k + r;
+    const int col = col0 + c;
+    if (vec && row < ke && col + S::VE <= ncol) {
+      typedef T vec_t __attribute__((ext_vector_type(GramStage<T>::VE)));
+      const vec_t v = *reinterpret_cast<const vec_t*>(X + row * ldx + col);
+#pragma unroll
+      for (int t = 0; t < S::VE; ++t) reg[u][t] = v[t];
+    } else {
+#pragma unroll
+      for (int t = 0; t < S::VE; ++t)
+        reg[u][t] = (row < ke && col + t < ncol) ? X[row * ldx + col + t] : (T)0;
+    }
+  }
+}
+
+template <class T>
+__device__ inline void gram_store(T* __restrict__ sm, const T (&reg)[GramStage<T>::PER][GramStage<T>::VE]) {
+  using S = GramStage<T>;
+#pragma unroll
+  for (int u = 0; u < S::PER; ++u) {
+    const int e = (u * 256 + (int)threadIdx.x) * S::VE;
+    const int r = e >> 6, c = e & 63;
+#pragma unroll
+    for (int t = 0; t < S::VE; ++t) sm[r * S::LD + c + t] = reg[u][t];
+  }
+}
+
 template <class T>
 __global__ __launch_bounds__(256) void k_gram(int64_t n, const T* __restrict__ A, int64_t lda,
                                               int p, const T* __restrict__ B, int64_t ldb, int q,
-                                              int sym, int64_t rows_per_split,
+                                              int sym, int vec, int64_t rows_per_split,
                                               double* __restrict__ part) {
   using M = Mfma<T>;
+  using S = GramStage<T>;
+  __shared__ T sa[kSlab * S::LD], sb[kSlab * S::LD];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wy = wave >> 1, wx = wave & 1;
   const int tiles_q = (q + 63) / 64;
@@ -71,57 +122,45 @@ __global__ __launch_bounds__(256) void k_gram(int64_t n, const T* __restrict__ A
     ty = blockIdx.x / tiles_q;
     tx = blockIdx.x % tiles_q;
   }
-  const int c0 = ty * 64 + wy * 32, d0 = tx * 64 + wx * 32;
+  const bool same = sym && ty == tx;  // one panel serves both operands
+  const T* sbp = same ? sa : sb;
   const int li = lane & 15, lk = lane >> 4;
   const int64_t kb = (int64_t)blockIdx.y * rows_per_split;
   const int64_t ke = min(n, kb + rows_per_split);
-  int ca[2], cb[2];
-  bool oka[2], okb[2];
-#pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    ca[u] = c0 + 16 * u + li;
-    cb[u] = d0 + 16 * u + li;
-    oka[u] = ca[u] < p;
-    okb[u] = cb[u] < q;
-  }
   typename M::acc acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = typename M::acc{0, 0, 0, 0};
-  // operands of 16 rows per step; the next step's are loaded before this
-  // step's MFMAs issue, so the loads overlap the matrix-core work
-  auto load = [&](int64_t k, T (&a)[4][2], T (&b)[4][2]) {
+  T ra[S::PER][S::VE], rb[S::PER][S::VE];
+  if (kb < ke) {
+    gram_load<T>(A, lda, p, ty * 64, kb, ke, vec != 0, ra);
+    if (!same) gram_load<T>(B, ldb, q, tx * 64, kb, ke, vec != 0, rb);
+  }
+  for (int64_t k = kb; k < ke; k += kSlab) {
+    __syncthreads();  // the previous slab's MFMAs are done with the LDS panels
+    gram_store<T>(sa, ra);
+    if (!same) gram_store<T>(sb, rb);
+    __syncthreads();
+    if (k + kSlab < ke) {
+      gram_load<T>(A, lda, p, ty * 64, k + kSlab, ke, vec != 0, ra);
+      if (!same) gram_load<T>(B, ldb, q, tx * 64, k + kSlab, ke, vec != 0, rb);
+    }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int64_t row = k + 4 * u + lk;
-      const bool ok = row < ke;
+    for (int kk = 0; kk < kSlab; kk += 4) {
+      T a[2], b[2];
 #pragma unroll
       for (int v = 0; v < 2; ++v) {
-        a[u][v] = (ok && oka[v]) ? A[row * lda + ca[v]] : (T)0;
-        b[u][v] = (ok && okb[v]) ? B[row * ldb + cb[v]] : (T)0;
+        a[v] = sa[(kk + lk) * S::LD + wy * 32 + 16 * v + li];
+        b[v] = sbp[(kk + lk) * S::LD + wx * 32 + 16 * v + li];
       }
-    }
-  };
-  T a[4][2], b[4][2];
-  if (kb < ke) load(kb, a, b);
-  for (int64_t k = kb; k < ke; k += 16) {
-    T an[4][2], bn[4][2];
-    load(k + 16, an, bn);  // rows at or past ke load as zeros
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = M::op(a[u][i], b[u][j], acc[i][j]);
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int v = 0; v < 2; ++v) {
-        a[u][v] = an[u][v];
-        b[u][v] = bn[u][v];
-      }
+        for (int j = 0; j < 2; ++j) acc[i][j] = M::op(a[i], b[j], acc[i][j]);
+    }
   }
+  const int c0 = ty * 64 + wy * 32, d0 = tx * 64 + wx * 32;
   double* out = part + (int64_t)blockIdx.y * p * q;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -269,12 +308,16 @@ void launch_gram(int64_t n, const T* A, int64_t lda, int p, const T* B, int64_t 
   int64_t splits = std::max<int64_t>(1, 1024 / tiles);
   splits = std::min<int64_t>(splits, std::max<int64_t>(1, (n + 255) / 256));
   int64_t rows = (n + splits - 1) / splits;
-  rows = ((rows + 15) / 16) * 16;
+  rows = ((rows + kSlab - 1) / kSlab) * kSlab;
   splits = std::max<int64_t>(1, (n + rows - 1) / rows);
   DevBuf part((size_t)splits * p * q * sizeof(double), s);
   if (n > 0) {
+    const uintptr_t align = reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B) |
+                            (uintptr_t)(lda * (int64_t)sizeof(T)) |
+                            (uintptr_t)(ldb * (int64_t)sizeof(T));
+    const int vec = (align % 16) == 0;
     hipLaunchKernelGGL(k_gram<T>, dim3(tiles, (unsigned)splits), dim3(256), 0, s, n, A, lda, p, B,
-                       ldb, q, sym, rows, part.as<double>());
+                       ldb, q, sym, vec, rows, part.as<double>());
     MBL_CHECK_LAUNCH();
   } else {
     MBL_HIP(hipMemsetAsync(part.get(), 0, part.bytes(), s));
