@@ -184,12 +184,19 @@ def run_serve(args):
     reqs = workloads.request_stream(args.count, rate_hz=1.0, Ls=Ls)
     probs = [{"L": r["L"], "h": r["h"], "eps": r["eps"], "nev": 16, "block": 32, "tol": 1e-10,
               "precision": args.serve_precision, "seed": 7} for r in reqs]
+    def note(msg):
+        print(f"[serve] {msg}", file=sys.stderr, flush=True)
+
     torch.cuda.init()
     api.batch_solve(probs[:2], concurrency=2)
-    # closed-loop capacity: all requests at once
-    t0 = time.perf_counter()
-    api.batch_solve(probs, concurrency=args.concurrency)
-    cap = len(probs) / (time.perf_counter() - t0)
+    # closed-loop capacity: all requests submitted at once
+    with api.Server(concurrency=args.concurrency) as srv:
+        t0 = time.perf_counter()
+        tickets = [srv.submit(d) for d in probs]
+        for i, t in enumerate(tickets):
+            srv.wait(t)
+            note(f"closed loop: request {i} (L={probs[i]['L']}) done at {time.perf_counter() - t0:.1f} s")
+        cap = len(probs) / (time.perf_counter() - t0)
     rate = args.load * cap
     gaps = np.random.default_rng(args.count).exponential(1.0 / rate, len(probs))
     results = [None] * len(probs)
@@ -201,6 +208,7 @@ def run_serve(args):
             tickets_ready.append(srv.submit(d))
         for i, t in enumerate(tickets_ready):
             results[i] = srv.wait(t)
+            note(f"open loop: request {i} (L={probs[i]['L']}) latency {results[i]['latency']:.2f} s")
         el = time.perf_counter() - t0
         st = srv.stats()
     lat = np.array([r["latency"] for r in results])
