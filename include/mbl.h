@@ -110,7 +110,10 @@ mbl_status mbl_diagonal(mbl_ham H, double sigma, double* diag_dev,
 
 /* Y = (H - sigma I) X for an n x b block, never forming H.  prec MBL_F64 or
  * MBL_F32 selects the element type of X and Y.  ldx, ldy >= b.  X and Y must
- * not overlap.  Async. */
+ * not overlap.  Async.  The launch schedule comes from the library's table of
+ * tuned schedules (nearest sector size, same row width); the environment
+ * variables MBL_APPLY_CHUNK_BYTES, MBL_APPLY_LANE_BYTES, MBL_APPLY_XCD_GROUP and
+ * MBL_APPLY_SLOTS_PER_XCD override its fields (they also apply to mbl_pcg). */
 mbl_status mbl_apply_block(mbl_ham H, double sigma, mbl_precision prec,
                            const void* X, int64_t ldx, void* Y, int64_t ldy,
                            int b, hipStream_t stream);

@@ -14,9 +14,11 @@
 // G*NV*VE contiguous elements per row: whole 128-byte lines for wide chunks.
 //
 // Work distribution: row tiles of 4 waves x 64/G rows; the grid is a multiple
-// of 8 and workgroup k runs on XCD k % 8, so each XCD gets one contiguous
-// range of tiles and the low-bond neighbours (offsets C(i,t) small) of its
-// rows stay in its own L2.
+// of 8 and workgroup k runs on XCD k % 8, so each XCD walks runs of
+// consecutive tiles and the low-bond neighbours (offsets C(i,t) small) of its
+// rows stay in its own L2.  The run length (tiles per XCD group), workgroups
+// per XCD, row-chunk and lane widths form the launch schedule, taken from a
+// table the package's autotuner measured (apply_schedules.inc).
 //
 // Column reductions (the CG dot products) are accumulated in FP64 per lane,
 // reduced across the wavefront with a fixed butterfly, across the 4 waves in
