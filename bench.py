@@ -32,7 +32,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBPS = 8000.0
 APPLY_SRC = [os.path.join(ROOT, "paper_2012_00217_amd", "csrc", f)
              for f in ("apply.hip", "apply_schedules.inc")]
-COUNTERS = os.path.join(ROOT, "profiles", "cg_apply_l20_counters.md")
+COUNTERS = os.path.join(ROOT, "profiles", "cg_apply_{}_counters.md")  # per workload
 
 WORKLOADS = {
     "l20": dict(L=20, Ws=[1.0, 2.0, 4.0, 8.0], seed=0, eps=0.5, nev=32, block=64, tol=1e-10,
@@ -62,9 +62,10 @@ def read_traffic(kernel, workload):
     """HBM bytes per launch from the committed counter summary, or None if the
     summary is missing, covers another workload or was taken from a different
     kernel source."""
-    if not os.path.exists(COUNTERS):
+    path = COUNTERS.format(workload)
+    if not os.path.exists(path):
         return None
-    txt = open(COUNTERS).read()
+    txt = open(path).read()
     m = re.search(r"counters_workload:\s*(\S+)", txt)
     if not m or m.group(1) != workload:
         return None
