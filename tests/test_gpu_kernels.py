@@ -73,6 +73,19 @@ def test_diagonal_and_jacobi(L, Sz, J, Delta):
     np.testing.assert_allclose(jac.cpu().numpy(), jd, rtol=1e-13)
 
 
+@pytest.mark.parametrize("L,Sz,J,Delta", [(11, 0.5, 0.7, -1.3), (16, 1.0, 1.3, 0.0), (13, -2.5, 2.0, 0.4)])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_apply_parity_other_sectors_and_couplings(L, Sz, J, Delta, dtype):
+    h, H = _ham(L, W=3.0, Sz=Sz, J=J, Delta=Delta)
+    st, Ho = _oracle(L, h, Sz, J, Delta)
+    X = workloads.random_block(H.n, 24, seed=L)
+    Xo = X.astype(np.float32).astype(np.float64) if dtype == torch.float32 else X
+    sigma = -0.41
+    Y = H.apply(torch.from_numpy(X).to(DEV, dtype), sigma).double().cpu().numpy()
+    tol = 1e-13 if dtype == torch.float64 else 2e-6
+    assert np.all(np.abs(Y - hamiltonian.apply_shifted(Ho, Xo, sigma)) <= tol * _abs_bound(Ho, Xo, sigma) + 1e-30)
+
+
 @pytest.mark.parametrize("b", [1, 3, 8, 16, 17, 64, 100])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_apply_parity_small(b, dtype):
