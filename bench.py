@@ -226,6 +226,20 @@ def run_serve(args):
            "throughput_pairs_per_s": round(pairs / el, 3),
            "capacity_req_per_s": round(cap, 4),
            "server_stats": {k: st[k] for k in ("completed", "rejected", "peak_bytes")}}
+    if args.plain:
+        # the plain path: the same requests solved one at a time in FP64, each
+        # latency being its own solve time (no queueing counted)
+        fp64 = [dict(d, precision="f64") for d in probs]
+        t0 = time.perf_counter()
+        res1 = api.batch_solve(fp64, concurrency=1)
+        el1 = time.perf_counter() - t0
+        note(f"plain FP64 one at a time: {el1:.1f} s")
+        lat1 = np.array([r["seconds"] for r in res1])
+        p1 = sum(int(np.sum(r["resid"] <= 1e-10)) for r in res1 if r["status"] == "MBL_OK")
+        out["plain_f64_one_at_a_time"] = {
+            "p50_ms": round(float(np.percentile(lat1, 50)) * 1e3, 1),
+            "p99_ms": round(float(np.percentile(lat1, 99)) * 1e3, 1),
+            "throughput_pairs_per_s": round(p1 / el1, 3), "ms": round(el1 * 1e3, 1)}
     print(json.dumps(out), flush=True)
 
 
@@ -286,7 +300,8 @@ def main():
                     choices=sorted(WORKLOADS) + ["batch", "serve", "gram"])
     ap.add_argument("--count", type=int, default=256, help="batch/serve: number of problems")
     ap.add_argument("--concurrency", type=int, default=8, help="batch/serve: concurrent solves")
-    ap.add_argument("--plain", action="store_true", help="batch: also solve one at a time")
+    ap.add_argument("--plain", action="store_true",
+                    help="batch/serve: also solve the same problems one at a time (serve: in FP64)")
     ap.add_argument("--serve-L", default="16,18,20")
     ap.add_argument("--serve-precision", default="mixed")
     ap.add_argument("--load", type=float, default=0.8, help="serve: arrival rate / capacity")
