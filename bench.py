@@ -191,25 +191,47 @@ def run_serve(args):
     torch.cuda.init()
     api.batch_solve(probs[:2], concurrency=2)
     # closed-loop capacity: all requests submitted at once
+    def drain(srv, pending, t0, tag, results=None):
+        # collect results in completion order, one progress line per request
+        while pending:
+            for i, t in list(pending.items()):
+                r = srv.wait(t, timeout=0.02)
+                if r is None:
+                    continue
+                del pending[i]
+                if results is not None:
+                    results[i] = r
+                note(f"{tag}: request {i} (L={probs[i]['L']}) done at "
+                     f"{time.perf_counter() - t0:.1f} s, latency {r['latency']:.2f} s")
+
     with api.Server(concurrency=args.concurrency) as srv:
         t0 = time.perf_counter()
-        tickets = [srv.submit(d) for d in probs]
-        for i, t in enumerate(tickets):
-            srv.wait(t)
-            note(f"closed loop: request {i} (L={probs[i]['L']}) done at {time.perf_counter() - t0:.1f} s")
+        drain(srv, {i: srv.submit(d) for i, d in enumerate(probs)}, t0, "closed loop")
         cap = len(probs) / (time.perf_counter() - t0)
     rate = args.load * cap
     gaps = np.random.default_rng(args.count).exponential(1.0 / rate, len(probs))
     results = [None] * len(probs)
     with api.Server(concurrency=args.concurrency) as srv:
         t0 = time.perf_counter()
-        tickets_ready = []
-        for i, d in enumerate(probs):
-            time.sleep(gaps[i])
-            tickets_ready.append(srv.submit(d))
-        for i, t in enumerate(tickets_ready):
-            results[i] = srv.wait(t)
-            note(f"open loop: request {i} (L={probs[i]['L']}) latency {results[i]['latency']:.2f} s")
+        arrive = np.cumsum(gaps)
+        pending, nxt = {}, 0
+        while nxt < len(probs) or pending:
+            now = time.perf_counter() - t0
+            while nxt < len(probs) and arrive[nxt] <= now:
+                pending[nxt] = srv.submit(probs[nxt])
+                note(f"open loop: request {nxt} (L={probs[nxt]['L']}) arrived at {now:.1f} s")
+                nxt += 1
+            if pending:
+                drain_once = dict(pending)
+                for i, t in drain_once.items():
+                    r = srv.wait(t, timeout=0.02)
+                    if r is not None:
+                        del pending[i]
+                        results[i] = r
+                        note(f"open loop: request {i} (L={probs[i]['L']}) done at "
+                             f"{time.perf_counter() - t0:.1f} s, latency {r['latency']:.2f} s")
+            else:
+                time.sleep(min(0.05, max(0.0, arrive[nxt] - now)))
         el = time.perf_counter() - t0
         st = srv.stats()
     lat = np.array([r["latency"] for r in results])

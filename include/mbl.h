@@ -275,7 +275,9 @@ mbl_status mbl_footprint_bytes(int L, double Sz, int block, int precision, size_
  * deterministic computation as mbl_lobpcg_solve, so a problem's result does
  * not depend on what runs beside it.  Per-problem outcomes are in results[i]
  * (status, sigma, counts, timings; evals/resid/evecs into caller buffers).
- * Returns MBL_OK if every problem converged, else the first problem's error. */
+ * Returns MBL_OK if every problem converged, else the first problem's error.
+ * With the environment variable MBL_VERBOSE=1, batch and server solves print
+ * one line per outer iteration to stderr. */
 mbl_status mbl_batch_solve(int count, const mbl_problem* problems, mbl_result* results,
                            int concurrency);
 

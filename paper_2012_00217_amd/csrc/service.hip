@@ -17,6 +17,7 @@
 #include <atomic>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <condition_variable>
 #include <deque>
 #include <map>
@@ -86,6 +87,9 @@ void run_problem(Job& j, double* evecs, int64_t ldv, hipStream_t s) {
     o.pcg_iters = p.pcg_iters;
     o.precision = p.precision;
     o.seed = p.seed ? p.seed : 0x5eed;
+    // MBL_VERBOSE=1: one stderr line per outer iteration of every solve
+    const char* verbose = std::getenv("MBL_VERBOSE");
+    o.verbose = verbose ? std::atoi(verbose) : 0;
     if (o.precision != MBL_F64 && o.precision != MBL_MIXED && o.precision != MBL_PCG32)
       fail(MBL_EINVAL, "bad precision");
     j.evals.assign(p.nev, 0.0);
