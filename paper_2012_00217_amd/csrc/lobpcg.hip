@@ -21,10 +21,13 @@
 //
 // Precision (MBL_MIXED): a first phase keeps every n-length block in FP32 (FP32
 // applies, FP32 combinations, FP32-MFMA Grams, FP32 PCG) while all small dense
-// algebra stays FP64; once the FP32 floor is reached the blocks are promoted
-// to FP64 and the iteration continues with FP64 blocks and FP32 PCG until the
-// requested tolerance.  MBL_PCG32 runs only the second kind of phase,
-// MBL_F64 runs FP64 everywhere.
+// algebra stays FP64; once that phase reaches 1e-4 or an iteration fails to
+// halve the residual, the blocks are promoted to FP64 and the iteration
+// continues with FP64 blocks and FP32 PCG until the requested tolerance.
+// MBL_PCG32 runs only the second kind of phase, MBL_F64 runs FP64 everywhere.
+//
+// Spectrum bounds: plain LOBPCG (block 4) on +H and -H with a Davidson-type
+// diagonal preconditioner W = R / max(|+-diag(H) - mu|, J/2).
 #include <algorithm>
 #include <chrono>
 #include <cmath>
