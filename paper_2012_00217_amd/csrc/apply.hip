@@ -30,7 +30,6 @@
 #include <cstdlib>
 
 #include "common.h"
-#include "split_plan.h"
 
 namespace mbl {
 namespace {
@@ -149,15 +148,7 @@ struct ApplyArgs {
   int L;
   int col0, w, log2G;
   TileSched ts;
-  // split apply: PART_NEAR takes bonds [0, split) and the diagonal; PART_FAR
-  // takes bonds [split, L-1) over the row segments seg_start/seg_len and adds
-  // to what PART_NEAR left in the output
-  int split;
-  const int64_t* seg_start;
-  const int* seg_len;
 };
-
-enum { PART_FULL = 0, PART_NEAR = 1, PART_FAR = 2 };
 
 constexpr int kWaves = 4;
 constexpr int kThreads = 64 * kWaves;
@@ -199,7 +190,7 @@ constexpr int kNoFlip = -2147483647 - 1;  // offset-table entry of an inactive b
 // 64 lanes, so each flip target is computed exactly once.  Phase B: the G
 // lanes of a row read four offsets at a time (one LDS load) and gather the
 // target rows' column chunks.
-template <class T, int VE, int NV, int EPI, int PART>
+template <class T, int VE, int NV, int EPI>
 __global__ __launch_bounds__(kThreads) void k_apply(ApplyArgs<T> a) {
   using P = Pack<T, VE>;
   constexpr int BB0 = MBL_APPLY_BB_BYTES / (NV * VE * (int)sizeof(T));
@@ -214,10 +205,7 @@ __global__ __launch_bounds__(kThreads) void k_apply(ApplyArgs<T> a) {
   const int rsub = lane >> a.log2G;
   const int cl = lane & (G - 1);
   const int nb = a.L - 1;
-  const int ib0 = (PART == PART_FAR) ? a.split : 0;            // bonds of this pass
-  const int ib1 = (PART == PART_NEAR) ? min(nb, a.split) : nb;
-  // partials of the column reductions come from full and far passes only
-  constexpr bool kReduce = (EPI != EPI_PLAIN) && (PART != PART_NEAR);
+  const uint32_t bondmask = nb > 0 ? ((1u << nb) - 1u) : 0u;
   const int cbase = a.col0 + cl * VE;  // first column of unit 0 of this lane
   const int red_doubles = (EPI == EPI_PLAIN) ? 0 : kWaves * a.w;
   int* offtab = reinterpret_cast<int*>(sdyn + red_doubles) + wave * (RW * 32);
@@ -242,22 +230,14 @@ __global__ __launch_bounds__(kThreads) void k_apply(ApplyArgs<T> a) {
     const int64_t tile = sched_tile(a.ts, u, xcd, &done);
     if (done) break;
     if (tile >= a.ts.ntiles) continue;
-    int64_t trow0, tend;  // rows [trow0, tend) of this tile
-    if constexpr (PART == PART_FAR) {
-      trow0 = a.seg_start[tile];
-      tend = trow0 + a.seg_len[tile];
-    } else {
-      trow0 = tile * (kWaves * RW);
-      tend = a.n;
-    }
-    const int64_t row0 = trow0 + wave * RW;  // first row of this wave
+    const int64_t row0 = tile * (kWaves * RW) + wave * RW;  // first row of this wave
 
     // Phase A: flip targets of the wave's RW rows, 32 bond slots per row.
     for (int it = lane; it < RW * 32; it += 64) {
       const int r = it >> 5, i = it & 31;
       const int64_t rr = row0 + r;
       int o = kNoFlip;
-      if (rr < tend && i >= ib0 && i < ib1) {
+      if (rr < a.n && i < nb) {
         const uint32_t sr = a.states[rr];
         if (((sr ^ (sr >> 1)) >> i) & 1u) {
           const int c = (int)C[i * kPascal + __popc(sr & ((1u << i) - 1u))];
@@ -275,18 +255,16 @@ __global__ __launch_bounds__(kThreads) void k_apply(ApplyArgs<T> a) {
 
     // Phase B: gather for this lane's row.
     const int64_t row = row0 + rsub;
-    if (row < tend) {
+    if (row < a.n) {
       const T* xrow = a.X + row * a.ldx + cbase;
       P own[NV];
-      if constexpr (PART != PART_FAR) {
 #pragma unroll
-        for (int q = 0; q < NV; ++q) own[q] = *reinterpret_cast<const P*>(xrow + q * G * VE);
-      }
+      for (int q = 0; q < NV; ++q) own[q] = *reinterpret_cast<const P*>(xrow + q * G * VE);
       T nbs[NV * VE];
 #pragma unroll
       for (int k = 0; k < NV * VE; ++k) nbs[k] = (T)0;
       const int* myoff = offtab + rsub * 32;
-      for (int i0 = ib0 & ~(BB - 1); i0 < ib1; i0 += BB) {
+      for (int i0 = 0; i0 < nb; i0 += BB) {
         int o[BB];
 #pragma unroll
         for (int v = 0; v < BB; ++v) o[v] = myoff[i0 + v];
@@ -311,69 +289,48 @@ __global__ __launch_bounds__(kThreads) void k_apply(ApplyArgs<T> a) {
 #pragma unroll
             for (int e = 0; e < VE; ++e) nbs[q * VE + e] += v[b2][q].v[e];
       }
+      const T ed = (T)(a.diag[row] - a.sigma);
       T acc[NV * VE];
-      if constexpr (PART == PART_FAR) {
 #pragma unroll
-        for (int k = 0; k < NV * VE; ++k) acc[k] = hj * nbs[k];
-      } else {
-        const T ed = (T)(a.diag[row] - a.sigma);
+      for (int q = 0; q < NV; ++q)
 #pragma unroll
-        for (int q = 0; q < NV; ++q)
-#pragma unroll
-          for (int e = 0; e < VE; ++e) acc[q * VE + e] = ed * own[q].v[e] + hj * nbs[q * VE + e];
-      }
+        for (int e = 0; e < VE; ++e) acc[q * VE + e] = ed * own[q].v[e] + hj * nbs[q * VE + e];
 
       if constexpr (EPI == EPI_PLAIN || EPI == EPI_NORM2) {
         T* yr = a.Y + row * a.ldy + cbase;
 #pragma unroll
         for (int q = 0; q < NV; ++q) {
           P o2;
-          if constexpr (PART == PART_FAR) {  // add to the near pass's result
-            o2 = *reinterpret_cast<const P*>(yr + q * G * VE);
 #pragma unroll
-            for (int e = 0; e < VE; ++e) {
-              o2.v[e] = o2.v[e] + acc[q * VE + e];
-              acc[q * VE + e] = o2.v[e];
-            }
-          } else {
-#pragma unroll
-            for (int e = 0; e < VE; ++e) o2.v[e] = acc[q * VE + e];
-          }
-          if constexpr (PART == PART_NEAR)
-            *reinterpret_cast<P*>(yr + q * G * VE) = o2;  // re-read by the far pass
-          else if constexpr (EPI == EPI_NORM2)
+          for (int e = 0; e < VE; ++e) o2.v[e] = acc[q * VE + e];
+          if constexpr (EPI == EPI_NORM2)
             store_cg_t<T, VE>(yr + q * G * VE, o2);
           else
             store_stream<T, VE>(yr + q * G * VE, o2);
         }
-        if constexpr (EPI == EPI_NORM2 && kReduce) {
+        if constexpr (EPI == EPI_NORM2) {
 #pragma unroll
           for (int k = 0; k < NV * VE; ++k) red[k] += (double)acc[k] * (double)acc[k];
         }
       } else {  // EPI_PCG
+        const T* pr = a.p + row * a.ldp + cbase;
+        T* xr = a.x + row * a.ldxv + cbase;
         T* rr = a.r + row * a.ldr + cbase;
         const T dinv = (T)1 / a.jac[row];
 #pragma unroll
         for (int q = 0; q < NV; ++q) {
+          P pv = load_once<T, VE>(pr + q * G * VE);
+          P xv = load_once<T, VE>(xr + q * G * VE);
           P rv = load_once<T, VE>(rr + q * G * VE);
-          if constexpr (PART != PART_FAR) {  // x += alpha p once, in the first pass
-            const T* pr = a.p + row * a.ldp + cbase;
-            T* xr = a.x + row * a.ldxv + cbase;
-            P pv = load_once<T, VE>(pr + q * G * VE);
-            P xv = load_once<T, VE>(xr + q * G * VE);
-#pragma unroll
-            for (int e = 0; e < VE; ++e) xv.v[e] = xv.v[e] + alpha[q * VE + e] * pv.v[e];
-            store_stream<T, VE>(xr + q * G * VE, xv);
-          }
 #pragma unroll
           for (int e = 0; e < VE; ++e) {
-            rv.v[e] = rv.v[e] - alpha[q * VE + e] * acc[q * VE + e];
-            if constexpr (kReduce) red[q * VE + e] += (double)rv.v[e] * (double)(rv.v[e] * dinv);
+            const T al = alpha[q * VE + e];
+            xv.v[e] = xv.v[e] + al * pv.v[e];
+            rv.v[e] = rv.v[e] - al * acc[q * VE + e];
+            red[q * VE + e] += (double)rv.v[e] * (double)(rv.v[e] * dinv);
           }
-          if constexpr (PART == PART_NEAR)
-            *reinterpret_cast<P*>(rr + q * G * VE) = rv;  // re-read by the far pass
-          else
-            store_stream<T, VE>(rr + q * G * VE, rv);
+          store_stream<T, VE>(xr + q * G * VE, xv);
+          store_stream<T, VE>(rr + q * G * VE, rv);
         }
       }
     }
@@ -382,7 +339,7 @@ __global__ __launch_bounds__(kThreads) void k_apply(ApplyArgs<T> a) {
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
-  if constexpr (kReduce) block_reduce_store<T, VE, NV>(red, a.log2G, a.w, a.part);
+  if constexpr (EPI != EPI_PLAIN) block_reduce_store<T, VE, NV>(red, a.log2G, a.w, a.part);
 }
 
 // PCG element-wise kernels with the same lane layout as k_apply.
@@ -522,7 +479,6 @@ int env_int(const char* name, int dflt) {
 // per lane, tiles per XCD group (0 = one group per XCD) and workgroups per XCD.
 struct Sched {
   int chunk_bytes, lane_bytes, grp, slots;
-  int split = 0;  // > 0: split apply with far bonds from this one on (0: one pass)
 };
 
 // Schedules measured best on the MI355X by the package's autotuner, keyed by
@@ -555,8 +511,6 @@ Sched sched_for(const Ham& H, int row_bytes, int elem) {
   best.lane_bytes = env_int("MBL_APPLY_LANE_BYTES", best.lane_bytes);
   best.grp = env_int("MBL_APPLY_XCD_GROUP", best.grp);
   best.slots = env_int("MBL_APPLY_SLOTS_PER_XCD", best.slots);
-  best.split = env_int("MBL_APPLY_SPLIT", best.split);
-  if (best.split <= 0 || best.split >= H.L - 1) best.split = 0;
   return best;
 }
 
@@ -610,49 +564,9 @@ Grid make_grid(int64_t n, int log2G, const Sched& sc) {
   return g;
 }
 
-// Grid of the far pass: its tiles are the plan's segments, dealt to the XCDs
-// in runs of consecutive segments (a run covers whole chunks, so each XCD's
-// L2 holds the rows its far bonds gather).
-Grid make_grid_tiles(int64_t ntiles, const Sched& sc) {
-  Grid g;
-  g.ts.ntiles = ntiles;
-  const int64_t per_xcd = (ntiles + 7) / 8;
-  const int grp = env_int("MBL_APPLY_FAR_GROUP", 256);
-  g.ts.grp = (int)std::max<int64_t>(1, std::min<int64_t>(grp > 0 ? grp : per_xcd, per_xcd));
-  const int64_t slots = std::min<int64_t>(per_xcd, std::min(256, std::max(1, sc.slots)));
-  g.nwg = (unsigned)(8 * std::max<int64_t>(1, slots));
-  return g;
-}
-
-// Segment plan of the far pass for (first far bond, rows per tile), built on
-// the host once per Hamiltonian and kept in device memory.
-const SplitPlan& split_plan(const Ham& H, int m, int tile_rows) {
-  std::lock_guard<std::mutex> lk(H.split_mu);
-  auto& slot = H.splits[{m, tile_rows}];
-  if (!slot) {
-    auto plan = std::make_unique<SplitPlan>();
-    std::vector<int64_t> st;
-    std::vector<int> len;
-    split_segments(H.L, H.nup, m, tile_rows, H.pascal_host.data(), kPascal, st, len);
-    plan->m = m;
-    plan->tile_rows = tile_rows;
-    plan->nseg = (int64_t)st.size();
-    plan->start.reset_persistent(std::max<size_t>(1, st.size()) * sizeof(int64_t));
-    plan->len.reset_persistent(std::max<size_t>(1, len.size()) * sizeof(int));
-    if (!st.empty()) {
-      MBL_HIP(hipMemcpy(plan->start.get(), st.data(), st.size() * sizeof(int64_t),
-                        hipMemcpyHostToDevice));
-      MBL_HIP(hipMemcpy(plan->len.get(), len.data(), len.size() * sizeof(int),
-                        hipMemcpyHostToDevice));
-    }
-    slot = std::move(plan);
-  }
-  return *slot;
-}
-
 constexpr int kMaxWg = 8 * 256;  // upper bound of Grid::nwg with the default knob
 
-template <class T, int EPI, int PART = PART_FULL>
+template <class T, int EPI>
 void dispatch_apply(const Chunk& ch, const Grid& g, ApplyArgs<T> a, hipStream_t s) {
   a.col0 = ch.col0;
   a.w = ch.w;
@@ -663,7 +577,7 @@ void dispatch_apply(const Chunk& ch, const Grid& g, ApplyArgs<T> a, hipStream_t 
   constexpr int VV = 16 / sizeof(T);
 #define MBL_APPLY_CASE(VE_, NV_)                                                             \
   if (ch.VE == VE_ && ch.NV == NV_) {                                                       \
-    hipLaunchKernelGGL((k_apply<T, VE_, NV_, EPI, PART>), dim3(g.nwg), dim3(kThreads), shm, s, a); \
+    hipLaunchKernelGGL((k_apply<T, VE_, NV_, EPI>), dim3(g.nwg), dim3(kThreads), shm, s, a); \
     MBL_CHECK_LAUNCH();                                                                     \
     return;                                                                                 \
   }
@@ -676,27 +590,6 @@ void dispatch_apply(const Chunk& ch, const Grid& g, ApplyArgs<T> a, hipStream_t 
   MBL_APPLY_CASE(1, 1)
 #undef MBL_APPLY_CASE
   fail(MBL_EINTERNAL, "apply: no kernel for chunk shape");
-}
-
-// One apply of a column chunk: a single pass, or the near pass (diagonal and
-// bonds below sc.split, in row order) followed by the far pass (the other
-// bonds, segment by segment).  Returns the grid whose workgroups wrote the
-// column partials (the one the finalize kernel must fold).
-template <class T, int EPI>
-Grid apply_chunk(const Ham& H, const Chunk& ch, const Grid& g, const Sched& sc, ApplyArgs<T> a,
-                 hipStream_t s) {
-  if (sc.split <= 0) {
-    dispatch_apply<T, EPI, PART_FULL>(ch, g, a, s);
-    return g;
-  }
-  const SplitPlan& plan = split_plan(H, sc.split, kWaves * (64 >> ch.log2G));
-  a.split = sc.split;
-  dispatch_apply<T, EPI, PART_NEAR>(ch, g, a, s);
-  const Grid gf = make_grid_tiles(plan.nseg, sc);
-  a.seg_start = plan.start.as<int64_t>();
-  a.seg_len = plan.len.as<int>();
-  dispatch_apply<T, EPI, PART_FAR>(ch, gf, a, s);
-  return gf;
 }
 
 template <class T, int MODE>
@@ -758,7 +651,7 @@ void launch_apply(const Ham& H, double sigma, const T* X, int64_t ldx, T* Y, int
   a.ldy = ldy;
   const Sched sc = sched_for(H, w * (int)sizeof(T), (int)sizeof(T));
   for (const Chunk& ch : plan_chunks<T>(w, aligned, sc))
-    apply_chunk<T, EPI_PLAIN>(H, ch, make_grid(H.n, ch.log2G, sc), sc, a, s);
+    dispatch_apply<T, EPI_PLAIN>(ch, make_grid(H.n, ch.log2G, sc), a, s);
 }
 
 // Block Jacobi-PCG on A = (H - sigma)^2, x0 = 0, m steps, per column:
@@ -861,25 +754,23 @@ void run_pcg(const Ham& H, double sigma, const T* jac, const T* R, int64_t ldr, 
       a2.part = part.as<double>();
       const int ntimed = tm ? std::min(m, PcgTiming::kSample) : 0;
       if (tm) tm->init();
-      // the far-pass segments (if any) exist before a step can be captured
-      if (sc.split > 0) split_plan(H, sc.split, kWaves * (64 >> ch.log2G));
       auto step = [&]() {
-        const Grid g1 = apply_chunk<T, EPI_NORM2>(H, ch, g, sc, a1, s);
-        finalize<FIN_ALPHA>(ch, g1, part.as<double>(), cf, s);
-        const Grid g2 = apply_chunk<T, EPI_PCG>(H, ch, g, sc, a2, s);
-        finalize<FIN_BETA>(ch, g2, part.as<double>(), cf, s);
+        dispatch_apply<T, EPI_NORM2>(ch, g, a1, s);
+        finalize<FIN_ALPHA>(ch, g, part.as<double>(), cf, s);
+        dispatch_apply<T, EPI_PCG>(ch, g, a2, s);
+        finalize<FIN_BETA>(ch, g, part.as<double>(), cf, s);
         dispatch_elt<T, ELT_PUPD>(ch, g, e, s);
       };
       int it = 0;
       for (; it < ntimed; ++it) {
         MBL_HIP(hipEventRecord(tm->ev[4 * it + 0], s));
-        const Grid g1 = apply_chunk<T, EPI_NORM2>(H, ch, g, sc, a1, s);
+        dispatch_apply<T, EPI_NORM2>(ch, g, a1, s);
         MBL_HIP(hipEventRecord(tm->ev[4 * it + 1], s));
-        finalize<FIN_ALPHA>(ch, g1, part.as<double>(), cf, s);
+        finalize<FIN_ALPHA>(ch, g, part.as<double>(), cf, s);
         MBL_HIP(hipEventRecord(tm->ev[4 * it + 2], s));
-        const Grid g2 = apply_chunk<T, EPI_PCG>(H, ch, g, sc, a2, s);
+        dispatch_apply<T, EPI_PCG>(ch, g, a2, s);
         MBL_HIP(hipEventRecord(tm->ev[4 * it + 3], s));
-        finalize<FIN_BETA>(ch, g2, part.as<double>(), cf, s);
+        finalize<FIN_BETA>(ch, g, part.as<double>(), cf, s);
         dispatch_elt<T, ELT_PUPD>(ch, g, e, s);
       }
       // The remaining steps replay one captured step: every CG coefficient

@@ -5,9 +5,6 @@
 
 #include <cstdint>
 #include <cstdio>
-#include <map>
-#include <memory>
-#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -91,16 +88,6 @@ class DevBuf {
 };
 
 // Per-sector Hamiltonian data (the opaque mbl_ham).
-// Row segments of the far-bond pass of a split apply (see apply.hip): the rows
-// with one high-bit pattern and one chunk of low-bit ranks, chunk by chunk.
-struct SplitPlan {
-  int m = 0;          // first far bond; sites >= m are the high bits
-  int tile_rows = 0;  // rows per segment at most (one workgroup tile)
-  int64_t nseg = 0;
-  DevBuf start;       // int64 [nseg] first row
-  DevBuf len;         // int32 [nseg] rows
-};
-
 struct Ham {
   int L = 0, nup = 0;
   int64_t n = 0;
@@ -112,9 +99,6 @@ struct Ham {
   DevBuf diag;     // double [n]  <s|H|s>
   DevBuf diag32;   // float  [n]  (same values rounded)
   std::vector<uint32_t> pascal_host;
-  // split-apply plans, built on first use and shared by every stream
-  mutable std::mutex split_mu;
-  mutable std::map<std::pair<int, int>, std::unique_ptr<SplitPlan>> splits;
 };
 
 // Host Pascal table C[i][t] (row-major, 33 x 33), 0 where t > i.

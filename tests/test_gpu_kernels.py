@@ -130,16 +130,12 @@ def test_apply_parity_full_size(L, b):
     assert np.all(np.abs(Y - Yr) <= 1e-13 * _abs_bound(Ho, X, sigma) + 1e-300)
 
 
-@pytest.mark.parametrize("L,b,dtype,split", [(24, 128, torch.float32, None), (24, 128, torch.float64, None),
-                                               (28, 32, torch.float64, None), (24, 128, torch.float32, 15),
-                                               (28, 32, torch.float64, 17)])
-def test_apply_sampled_rows_at_full_size(L, b, dtype, split, monkeypatch):
+@pytest.mark.parametrize("L,b,dtype", [(24, 128, torch.float32), (24, 128, torch.float64),
+                                         (28, 32, torch.float64)])
+def test_apply_sampled_rows_at_full_size(L, b, dtype):
     """The applies of the L = 24 (block 128, FP32 and FP64) and L = 28 (block 32,
-    FP64) workloads in the launch configuration the solver uses (and with a
-    forced split apply): 600 sampled rows (first, last, tile edges, random)
-    against the oracle's row-wise apply."""
-    if split is not None:
-        monkeypatch.setenv("MBL_APPLY_SPLIT", str(split))
+    FP64) workloads in the launch configuration the solver uses: 600 sampled
+    rows (first, last, tile edges, random) against the oracle's row-wise apply."""
     h, H = _ham(L, W=4.0)
     g = torch.Generator(device=DEV)
     g.manual_seed(L * 1000 + b)
@@ -216,16 +212,13 @@ def test_pcg_parity(m, b):
 # Launch schedules the autotuner may choose: (chunk bytes, lane bytes, tiles per
 # XCD group, workgroups per XCD).  Each must give the same applies (the per-row
 # arithmetic does not depend on the schedule) and oracle-exact CG.
-# The fifth field is the first far bond of a split apply (0: one pass); a split
-# changes only the order in which a row's bond terms are added.
-SCHEDULES = [(128, 16, 4, 128, 0), (256, 32, 16, 256, 0), (256, 64, 64, 64, 0), (512, 64, 1, 3, 0),
-             (128, 32, 0, 256, 0), (512, 64, 0, 256, 8), (256, 32, 16, 256, 5), (128, 16, 4, 64, 11),
-             (512, 64, 64, 256, 1)]
+SCHEDULES = [(128, 16, 4, 128), (256, 32, 16, 256), (256, 64, 64, 64), (512, 64, 1, 3),
+             (128, 32, 0, 256)]
 
 
 def _set_schedule(monkeypatch, sc):
     for k, v in zip(("MBL_APPLY_CHUNK_BYTES", "MBL_APPLY_LANE_BYTES", "MBL_APPLY_XCD_GROUP",
-                     "MBL_APPLY_SLOTS_PER_XCD", "MBL_APPLY_SPLIT"), sc):
+                     "MBL_APPLY_SLOTS_PER_XCD"), sc):
         monkeypatch.setenv(k, str(v))
 
 
@@ -242,8 +235,7 @@ def test_apply_and_pcg_under_every_schedule(sc, dtype, b, monkeypatch):
     ref = H.apply(Xd, sigma)  # default schedule
     _set_schedule(monkeypatch, sc)
     Y = H.apply(Xd, sigma)
-    if sc[4] == 0:
-        assert torch.equal(Y, ref)
+    assert torch.equal(Y, ref)
     tol = 1e-13 if dtype == torch.float64 else 2e-6
     Yr = hamiltonian.apply_shifted(Ho, Xo, sigma)
     assert np.all(np.abs(Y.double().cpu().numpy() - Yr) <= tol * _abs_bound(Ho, Xo, sigma) + 1e-30)
