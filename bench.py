@@ -330,6 +330,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verbose", action="store_true", help="one line per outer iteration")
     ap.add_argument("--max-iter", type=int, default=400, help="outer LOBPCG iterations per solve")
+    ap.add_argument("--pcg-iters", type=int, default=0,
+                    help="CG steps per outer iteration (0: the library default)")
     ap.add_argument("--cg-only", type=int, default=0,
                     help="counter runs: only run this many CG steps per realisation")
     args = ap.parse_args()
@@ -384,7 +386,7 @@ def main():
             ev, V, rs, info = H.solve(sigmas[W], wl["nev"], wl["block"], tol=wl["tol"],
                                       precision=wl["precision"], timing=True,
                                       raise_on_noconv=False, verbose=args.verbose,
-                                      max_iter=args.max_iter)
+                                      max_iter=args.max_iter, pcg_iters=args.pcg_iters)
             if record:
                 out[W] = dict(info=info, evals=ev, resid=rs, V=V)
         return out
