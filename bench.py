@@ -320,7 +320,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--workload", default="l20",
                     choices=sorted(WORKLOADS) + ["batch", "serve", "gram"])
-    ap.add_argument("--count", type=int, default=256, help="batch/serve: number of problems")
+    ap.add_argument("--count", type=int, default=0,
+                    help="batch/serve: number of problems (default 256 for batch, 40 for serve)")
     ap.add_argument("--concurrency", type=int, default=8, help="batch/serve: concurrent solves")
     ap.add_argument("--plain", action="store_true",
                     help="batch/serve: also solve the same problems one at a time (serve: in FP64)")
@@ -335,6 +336,8 @@ def main():
     ap.add_argument("--cg-only", type=int, default=0,
                     help="counter runs: only run this many CG steps per realisation")
     args = ap.parse_args()
+    if args.count <= 0:
+        args.count = 40 if args.workload == "serve" else 256
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
