@@ -331,6 +331,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verbose", action="store_true", help="one line per outer iteration")
     ap.add_argument("--max-iter", type=int, default=400, help="outer LOBPCG iterations per solve")
+    ap.add_argument("--precision", default="", choices=["", "f64", "pcg32", "mixed"],
+                    help="override the workload's precision")
     ap.add_argument("--pcg-iters", type=int, default=0,
                     help="CG steps per outer iteration (0: the library default)")
     ap.add_argument("--cg-only", type=int, default=0,
@@ -354,7 +356,10 @@ def main():
     import torch
     from paper_2012_00217_amd import api, workloads
 
-    wl = WORKLOADS[args.workload]
+    wl = dict(WORKLOADS[args.workload])
+    if args.precision and args.precision != wl["precision"]:
+        wl["desc"] = wl["desc"].rsplit(", ", 1)[0] + f", precision {args.precision}"
+        wl["precision"] = args.precision
     L = wl["L"]
     torch.cuda.init()
     hams, sigmas = {}, {}
