@@ -58,16 +58,19 @@ def apply_src_hash():
     return h.hexdigest()[:16]
 
 
-def read_traffic(kernel, workload):
+def read_traffic(kernel, workload, precision):
     """HBM bytes per launch from the committed counter summary, or None if the
-    summary is missing, covers another workload or was taken from a different
-    kernel source."""
+    summary is missing, covers another workload or precision, or was taken
+    from a different kernel source."""
     path = COUNTERS.format(workload)
     if not os.path.exists(path):
         return None
     txt = open(path).read()
     m = re.search(r"counters_workload:\s*(\S+)", txt)
     if not m or m.group(1) != workload:
+        return None
+    m = re.search(r"counters_precision:\s*(\S+)", txt)
+    if not m or m.group(1) != precision:
         return None
     m = re.search(r"apply_src_sha256_16:\s*([0-9a-f]+)", txt)
     if not m or m.group(1) != apply_src_hash():
@@ -435,7 +438,7 @@ def main():
     dom = max(tot, key=lambda kk: tot[kk][1])
     kb = tot[dom][2] / max(1, tot[dom][0])
     achieved = kb / (avg[dom] * 1e-3) / 1e9
-    traffic = read_traffic(dom, args.workload)
+    traffic = read_traffic(dom, args.workload, wl["precision"])
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
                 "kernel": f"k_apply fused CG {dom} ({'FP64' if s == 8 else 'FP32'}, "

@@ -33,12 +33,14 @@ def test_traffic_is_taken_only_from_matching_counter_files():
     b = importlib.util.module_from_spec(spec)
     spec.loader.exec_module(b)
     # no counter file for this workload
-    assert b.read_traffic("apply2", "l12") is None
+    assert b.read_traffic("apply2", "l12", "f64") is None
+    # counters of the mixed-precision L=24 workload do not describe an FP64 run of it
+    assert b.read_traffic("apply2", "l24", "f64") is None
     # the committed files carry their workload and the source hash they were taken with
-    for wl in ("l20", "l24"):
+    for wl, prec in (("l20", "f64"), ("l24", "mixed")):
         txt = open(os.path.join(ROOT, "profiles", f"cg_apply_{wl}_counters.md")).read()
-        assert f"counters_workload: {wl}" in txt
-        t = b.read_traffic("apply2", wl)
+        assert f"counters_workload: {wl}" in txt and f"counters_precision: {prec}" in txt
+        t = b.read_traffic("apply2", wl, prec)
         if f"apply_src_sha256_16: {b.apply_src_hash()}" in txt:
             assert t is not None and t > 0
         else:
