@@ -246,6 +246,28 @@ def test_apply_and_pcg_under_every_schedule(sc, dtype, b, monkeypatch):
         np.testing.assert_allclose(W, Wr, rtol=0, atol=1e-9 * np.abs(Wr).max())
 
 
+@pytest.mark.parametrize("L,b,dtype,m", [(20, 64, torch.float64, 8), (24, 128, torch.float32, 2)])
+def test_pcg_at_full_size(L, b, dtype, m):
+    """The block Jacobi-PCG of the L=20 (FP64, 64 columns, 8 steps: the captured
+    graph path) and L=24 (FP32 CG, 128 columns) workloads in the launch
+    configuration the solver uses, against the oracle's step-by-step PCG."""
+    h, H = _ham(L, W=4.0)
+    st, Ho = _oracle(L, h)
+    sigma = -0.37
+    R = workloads.random_block(H.n, b, seed=L)
+    Rd = torch.from_numpy(R).to(DEV, dtype)
+    Ro = Rd.double().cpu().numpy()
+    W = H.pcg(Rd, sigma, m).double().cpu().numpy()
+    del Rd
+    torch.cuda.empty_cache()
+    Wr = opcg.pcg_fold(Ho, sigma, hamiltonian.fold_diagonal(Ho, sigma), Ro, m)
+    if dtype == torch.float64:
+        np.testing.assert_allclose(W, Wr, rtol=0, atol=1e-9 * np.abs(Wr).max())
+    else:
+        rel = np.linalg.norm(W - Wr, axis=0) / np.linalg.norm(Wr, axis=0)
+        assert rel.max() <= 1e-3, rel.max()
+
+
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_pcg_column_chunks_agree(dtype, monkeypatch):
     """Solving the block CG in cache-sized column chunks (ragged last chunk)

@@ -54,8 +54,9 @@ def test_cfg1_l12_dense_parity(precision):
     _check(Ho, sigma, nev, ev, V, rs, w_ref, V_ref)
 
 
+@pytest.mark.parametrize("precision", ["f64", "mixed"])
 @pytest.mark.parametrize("L,Sz,J,Delta,eps", [(13, 0.5, 0.8, 1.7, 0.3), (14, -1.0, 1.2, 0.5, 0.7)])
-def test_other_sectors_and_couplings_dense_parity(L, Sz, J, Delta, eps):
+def test_other_sectors_and_couplings_dense_parity(L, Sz, J, Delta, eps, precision):
     """Odd L, S^z != 0, J != 1 and Delta != 1 through the whole solver."""
     nev, b = 6, 12
     h = workloads.disorder(L, 5.0, 3)
@@ -68,7 +69,7 @@ def test_other_sectors_and_couplings_dense_parity(L, Sz, J, Delta, eps):
     assert H.n == len(st)
     glo, ghi = H.spectrum_bounds(1e-12)
     assert abs(glo - emin) < 1e-10 and abs(ghi - emax) < 1e-10
-    ev, V, rs, info = H.solve(sigma, nev, b, tol=1e-10)
+    ev, V, rs, info = H.solve(sigma, nev, b, tol=1e-10, precision=precision)
     assert info["status"] == "MBL_OK"
     _check(Ho, sigma, nev, ev, V, rs, w_ref, V_ref)
 
