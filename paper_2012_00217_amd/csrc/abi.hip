@@ -184,12 +184,29 @@ mbl_status mbl_hamiltonian_dim(mbl_ham h, int64_t* n) {
   });
 }
 
+// A non-blocking stream for the entry points that take none: work on the
+// legacy stream would have to wait for (or break) hipGraph captures that other
+// threads of the process may have in progress.
+struct PrivateStream {
+  hipStream_t s = nullptr;
+  PrivateStream() { MBL_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking)); }
+  ~PrivateStream() {
+    if (s) {
+      (void)hipStreamSynchronize(s);
+      (void)hipStreamDestroy(s);
+    }
+  }
+};
+
 mbl_status mbl_sector_states(mbl_ham h, uint64_t* states_host) {
   return guard([&] {
     const Ham& H = ham(h);
     require(states_host != nullptr, "states is NULL");
     std::vector<uint32_t> tmp((size_t)H.n);
-    MBL_HIP(hipMemcpy(tmp.data(), H.states.get(), (size_t)H.n * sizeof(uint32_t), hipMemcpyDeviceToHost));
+    PrivateStream ps;
+    MBL_HIP(hipMemcpyAsync(tmp.data(), H.states.get(), (size_t)H.n * sizeof(uint32_t),
+                           hipMemcpyDeviceToHost, ps.s));
+    MBL_HIP(hipStreamSynchronize(ps.s));
     for (int64_t i = 0; i < H.n; ++i) states_host[i] = tmp[(size_t)i];
     return MBL_OK;
   });
@@ -201,10 +218,14 @@ mbl_status mbl_rank(mbl_ham h, const uint64_t* states_host, int64_t count, int64
     require(count >= 0, "count < 0");
     if (count == 0) return MBL_OK;
     require(states_host && idx_host, "NULL array");
-    DevBuf q((size_t)count * sizeof(uint64_t), nullptr), r((size_t)count * sizeof(int64_t), nullptr);
-    MBL_HIP(hipMemcpy(q.get(), states_host, q.bytes(), hipMemcpyHostToDevice));
-    rank_states(H, q.as<uint64_t>(), count, r.as<int64_t>(), nullptr);
-    MBL_HIP(hipMemcpy(idx_host, r.get(), r.bytes(), hipMemcpyDeviceToHost));
+    PrivateStream ps;
+    {
+      DevBuf q((size_t)count * sizeof(uint64_t), ps.s), r((size_t)count * sizeof(int64_t), ps.s);
+      MBL_HIP(hipMemcpyAsync(q.get(), states_host, q.bytes(), hipMemcpyHostToDevice, ps.s));
+      rank_states(H, q.as<uint64_t>(), count, r.as<int64_t>(), ps.s);
+      MBL_HIP(hipMemcpyAsync(idx_host, r.get(), r.bytes(), hipMemcpyDeviceToHost, ps.s));
+      MBL_HIP(hipStreamSynchronize(ps.s));
+    }
     return MBL_OK;
   });
 }

@@ -776,11 +776,13 @@ void run_pcg(const Ham& H, double sigma, const T* jac, const T* R, int64_t ldr, 
       // The remaining steps replay one captured step: every CG coefficient
       // lives on the device, so the five launches are identical each step.
       if (env_int("MBL_PCG_GRAPH", 1) != 0 && m - it >= 8) {
-        // the legacy default stream cannot be captured: fork onto a private
-        // stream (ordered after s by an event) and join back afterwards
+        // capture on a private non-blocking stream (ordered after s by an
+        // event, joined back afterwards): the legacy default stream cannot be
+        // captured, and a capture on a caller's blocking stream would forbid
+        // legacy-stream work in every other thread of the process meanwhile
         hipStream_t cs = s, own = nullptr;
         hipEvent_t fork = nullptr, join = nullptr;
-        if (s == nullptr) {
+        {
           MBL_HIP(hipStreamCreateWithFlags(&own, hipStreamNonBlocking));
           MBL_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
           MBL_HIP(hipEventCreateWithFlags(&join, hipEventDisableTiming));

@@ -192,6 +192,9 @@ struct Server {
   bool stop = false;
   clk::time_point created = clk::now();
   std::vector<std::thread> workers;
+  // copies of results to the caller: a stream of its own, never the legacy
+  // stream, which would have to wait for the workers' captured CG steps
+  hipStream_t copy = nullptr;
 
   void worker_loop() {
     (void)hipSetDevice(dev);
@@ -257,6 +260,7 @@ mbl_status server_create(int conc, size_t budget, Server** out) {
     budget = (size_t)(0.9 * (double)fr);
   }
   srv->budget = budget;
+  srv->copy = new_stream();
   Server* raw = srv.get();
   for (int t = 0; t < std::max(1, conc); ++t) raw->workers.emplace_back([raw] { raw->worker_loop(); });
   *out = srv.release();
@@ -303,10 +307,12 @@ mbl_status server_wait(Server* srv, uint64_t ticket, double timeout_s, mbl_resul
     return MBL_ETIMEOUT;
   }
   copy_out(*j, out);
-  if (out->evecs_dev && j->V.get() && j->n > 0)
-    MBL_HIP(hipMemcpy2D(out->evecs_dev, out->ldv * sizeof(double), j->V.get(),
-                        j->p.nev * sizeof(double), j->p.nev * sizeof(double), j->n,
-                        hipMemcpyDeviceToDevice));
+  if (out->evecs_dev && j->V.get() && j->n > 0) {
+    MBL_HIP(hipMemcpy2DAsync(out->evecs_dev, out->ldv * sizeof(double), j->V.get(),
+                             j->p.nev * sizeof(double), j->p.nev * sizeof(double), j->n,
+                             hipMemcpyDeviceToDevice, srv->copy));
+    MBL_HIP(hipStreamSynchronize(srv->copy));
+  }
   srv->jobs.erase(it);
   return MBL_OK;
 }
@@ -342,6 +348,7 @@ void server_destroy(Server* srv) {
   }
   srv->cv_work.notify_all();
   for (auto& t : srv->workers) t.join();
+  if (srv->copy) (void)hipStreamDestroy(srv->copy);
   delete srv;
 }
 

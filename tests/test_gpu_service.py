@@ -2,6 +2,8 @@
 (bitwise: every solve is a deterministic kernel sequence), parity with the
 oracle on a stratified sample, footprint admission and server statistics."""
 
+import math
+
 import numpy as np
 import pytest
 import torch
@@ -51,7 +53,7 @@ def test_server_results_equal_alone_and_in_the_mix():
         tickets = [srv.submit(dict(d, want_vectors=True)) for d in probs]
         outs = []
         for t, d in zip(tickets, probs):
-            V = torch.empty((api.Hamiltonian(d["L"], d["h"]).n, d["nev"]), dtype=torch.float64,
+            V = torch.empty((math.comb(d["L"], d["L"] // 2), d["nev"]), dtype=torch.float64,
                             device="cuda")
             r = srv.wait(t, vectors_out=V)
             outs.append((r, V))
@@ -85,3 +87,26 @@ def test_server_wait_timeout_returns_none():
         assert srv.wait(t, timeout=0.0) is None
         r = srv.wait(t)
         assert r["status"] == "MBL_OK"
+
+
+def test_heterogeneous_mix_equals_alone_and_oracle():
+    """Precisions, odd L with S^z = 1/2 and other couplings served side by side:
+    every result is bitwise the one-at-a-time result and matches the oracle."""
+    specs = [(13, 0.5, 1.0, 1.0, "mixed"), (12, 1.0, 0.8, 1.6, "pcg32"), (14, 0.0, 1.0, 0.0, "f64"),
+             (11, -0.5, 1.2, 0.7, "mixed"), (12, 0.0, 1.0, 1.0, "pcg32")]
+    probs = []
+    for j, (L, Sz, J, Delta, prec) in enumerate(specs):
+        probs.append({"L": L, "Sz": Sz, "J": J, "Delta": Delta, "h": workloads.disorder(L, 5.0, 200 + j),
+                      "eps": 0.3 + 0.1 * j, "nev": 6, "block": 12, "tol": 1e-10, "precision": prec,
+                      "seed": 11})
+    with api.Server(concurrency=4) as srv:
+        tickets = [srv.submit(d) for d in probs]
+        mixed = [srv.wait(t) for t in tickets]
+    alone = api.batch_solve(probs, concurrency=1)
+    for d, r, a in zip(probs, mixed, alone):
+        assert r["status"] == "MBL_OK", r
+        assert np.array_equal(r["evals"], a["evals"])
+        k = int(round(d["Sz"] + d["L"] / 2))
+        st, Ho = hamiltonian.sector_matrix(d["L"], k, d["J"], d["Delta"], d["h"])
+        w_ref, _ = spectrum.nearest(Ho, r["sigma"], d["nev"])
+        assert np.max(np.abs(r["evals"] - w_ref)) <= 1e-10
