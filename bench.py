@@ -338,6 +338,8 @@ def main():
                     help="override the workload's precision")
     ap.add_argument("--pcg-iters", type=int, default=0,
                     help="CG steps per outer iteration (0: the library default)")
+    ap.add_argument("--lock", action="store_true",
+                    help="single solves: soft locking of converged pairs (mbl_solve_opts.lock)")
     ap.add_argument("--cg-only", type=int, default=0,
                     help="counter runs: only run this many CG steps per realisation")
     args = ap.parse_args()
@@ -397,7 +399,8 @@ def main():
             ev, V, rs, info = H.solve(sigmas[W], wl["nev"], wl["block"], tol=wl["tol"],
                                       precision=wl["precision"], timing=True,
                                       raise_on_noconv=False, verbose=args.verbose,
-                                      max_iter=args.max_iter, pcg_iters=args.pcg_iters)
+                                      max_iter=args.max_iter, pcg_iters=args.pcg_iters,
+                                      lock=args.lock)
             if record:
                 out[W] = dict(info=info, evals=ev, resid=rs, V=V)
         return out
@@ -438,11 +441,13 @@ def main():
     dom = max(tot, key=lambda kk: tot[kk][1])
     kb = tot[dom][2] / max(1, tot[dom][0])
     achieved = kb / (avg[dom] * 1e-3) / 1e9
-    traffic = read_traffic(dom, args.workload, wl["precision"])
+    # the counters were taken on full-width launches; soft locking mixes widths
+    traffic = None if args.lock else read_traffic(dom, args.workload, wl["precision"])
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
                 "kernel": f"k_apply fused CG {dom} ({'FP64' if s == 8 else 'FP32'}, "
-                          f"{wl['block']}-column block)",
+                          f"{wl['block']}-column block"
+                          f"{', narrower once pairs lock' if args.lock else ''})",
                 "algorithmic_bytes_per_launch": kb, "avg_launch_us": round(avg[dom] * 1e3, 2),
                 "timed_launches": tot[dom][0]}
 
@@ -476,6 +481,7 @@ def main():
     last = runs[-1]
     per_w = {str(W): {"sigma": sigmas[W], "iters": r["info"]["iters"],
                       "applies": r["info"]["applies"], "pcg_steps": r["info"]["pcg_steps"],
+                      "pcg_columns": r["info"]["pcg_columns"],
                       "seconds": round(r["info"]["seconds"], 3),
                       "max_resid": float(np.max(r["resid"])), "status": r["info"]["status"]}
              for W, r in last.items()}
@@ -500,7 +506,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl["desc"], "L": L, "n": n, "nev": wl["nev"],
                    "block": wl["block"], "tol": wl["tol"], "precision": wl["precision"],
-                   "W": wl["Ws"], "pairs_per_step": pairs // args.steps},
+                   "W": wl["Ws"], "pairs_per_step": pairs // args.steps,
+                   **({"soft_locking": True} if args.lock else {})},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "hx_GBps": round(hx_gbps, 1),

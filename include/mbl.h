@@ -171,6 +171,17 @@ typedef struct {
                             events on the solve's stream (first 64 CG steps
                             of every inner solve)                            */
   uint64_t seed;         /* starting block (device counter-based generator)  */
+  int lock;              /* 1: soft locking.  Wanted pairs whose tracked
+                            residual is <= tol/10 keep their place in X and
+                            in every Rayleigh-Ritz step but get no new
+                            preconditioned direction: the fold residual is
+                            rotated into the H-Ritz basis of span(X), their
+                            columns are left out, and the remaining width is
+                            rounded up to whole 128-byte rows of the CG's
+                            scalars (least converged locked pairs stay
+                            active), so the inner CG runs on fewer columns.
+                            Results satisfy the same tolerance; iterates
+                            differ from lock = 0.  Default 0.               */
 } mbl_solve_opts;
 
 typedef struct {
@@ -191,6 +202,8 @@ typedef struct {
   /* algorithmic bytes of those launches: apply1 2nws + 12n, apply2
      6nws + (12 + s)n for a launch over w columns of s-byte scalars          */
   double cg_apply1_bytes[2], cg_apply2_bytes[2];
+  int64_t pcg_columns;   /* CG steps times block columns, summed over inner
+                            solves (fewer than pcg_steps * block with lock) */
 } mbl_solve_info;
 
 mbl_status mbl_solve_opts_default(mbl_solve_opts* opts);

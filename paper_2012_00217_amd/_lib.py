@@ -21,7 +21,8 @@ STATUS_NAMES = {0: "MBL_OK", -1: "MBL_EINVAL", -2: "MBL_ENOMEM", -3: "MBL_EDEVIC
 
 class SolveOpts(C.Structure):
     _fields_ = [("max_iter", C.c_int), ("pcg_iters", C.c_int), ("precision", C.c_int),
-                ("verbose", C.c_int), ("timing", C.c_int), ("seed", C.c_uint64)]
+                ("verbose", C.c_int), ("timing", C.c_int), ("seed", C.c_uint64),
+                ("lock", C.c_int)]
 
 
 class SolveInfo(C.Structure):
@@ -30,7 +31,8 @@ class SolveInfo(C.Structure):
                 ("t_pcg", C.c_double), ("t_rr", C.c_double), ("max_resid", C.c_double),
                 ("cg_apply1_launches", C.c_int64 * 2), ("cg_apply2_launches", C.c_int64 * 2),
                 ("cg_apply1_ms", C.c_double * 2), ("cg_apply2_ms", C.c_double * 2),
-                ("cg_apply1_bytes", C.c_double * 2), ("cg_apply2_bytes", C.c_double * 2)]
+                ("cg_apply1_bytes", C.c_double * 2), ("cg_apply2_bytes", C.c_double * 2),
+                ("pcg_columns", C.c_int64)]
 
 
 class Problem(C.Structure):

@@ -143,7 +143,7 @@ class Hamiltonian:
         return S
 
     def solve_slices(self, sigmas, nev, block, tol=1e-10, precision="f64", concurrency=4,
-                     max_iter=400, pcg_iters=0, seed=0x5EED):
+                     max_iter=400, pcg_iters=0, seed=0x5EED, lock=False):
         """Eigenvalue chunks: the nev pairs nearest each shift (values and residuals)."""
         lib = _lib.load()
         sig = np.ascontiguousarray(np.asarray(sigmas, dtype=np.float64))
@@ -151,6 +151,7 @@ class Hamiltonian:
         _lib.check(lib.mbl_solve_opts_default(C.byref(opts)))
         opts.max_iter, opts.pcg_iters, opts.seed = int(max_iter), int(pcg_iters), int(seed)
         opts.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        opts.lock = int(bool(lock))
         ev = np.zeros((len(sig), nev))
         rs = np.zeros((len(sig), nev))
         _lib.check(lib.mbl_slices_solve(self._h, len(sig), sig.ctypes.data_as(_lib.dptr), int(nev),
@@ -161,8 +162,11 @@ class Hamiltonian:
 
     def solve(self, sigma, nev, block, tol=1e-10, precision="f64", max_iter=400, pcg_iters=0,
               seed=0x5EED, verbose=False, want_vectors=True, device="cuda", stream=None,
-              raise_on_noconv=True, timing=False):
+              raise_on_noconv=True, timing=False, lock=False):
         """nev eigenpairs nearest sigma by LOBPCG on the spectral fold.
+
+        lock=True turns on soft locking of converged wanted pairs (the inner
+        CG then runs on fewer columns; see mbl_solve_opts.lock).
 
         Returns (evals [nev] numpy, evecs (n, nev) float64 tensor or None,
         resid [nev] numpy, info dict).
@@ -176,6 +180,7 @@ class Hamiltonian:
         opts.verbose = int(bool(verbose))
         opts.timing = int(bool(timing))
         opts.seed = int(seed)
+        opts.lock = int(bool(lock))
         ev = np.zeros(nev)
         rs = np.zeros(nev)
         info = _lib.SolveInfo()

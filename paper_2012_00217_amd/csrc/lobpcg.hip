@@ -18,6 +18,9 @@
 //   values theta of H - sigma; the nev with smallest |theta| are the wanted
 //   pairs, accepted when ||(H - sigma) x - theta x||_2 <= tol.  Before
 //   returning, the residuals are recomputed with a fresh FP64 apply.
+//   Soft locking (option): wanted pairs whose residual is below tol/10 stay
+//   in X and in every Rayleigh-Ritz step but get no new W direction, so the
+//   inner CG runs on fewer columns once the pairs nearest sigma converge.
 //
 // Precision (MBL_MIXED): a first phase keeps every n-length block in FP32 (FP32
 // applies, FP32 combinations, FP32-MFMA Grams, FP32 PCG) while all small dense
@@ -32,6 +35,8 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <utility>
+#include <vector>
 
 #include "common.h"
 
@@ -62,11 +67,12 @@ struct Params {
   bool fold = true;   // false: plain LOBPCG on sign * (H - sigma)
   double sign = 1.0;
   bool diag_precond = false;  // plain mode: W = R / |sign*diag(H) - mu| instead of W = R
+  double lock_tol = 0;        // > 0: soft locking of wanted pairs with residual <= lock_tol
 };
 
 struct Stats {
   int iters = 0, iters_fp64 = 0;
-  int64_t applies = 0, pcg_steps = 0;
+  int64_t applies = 0, pcg_steps = 0, pcg_columns = 0;
   double t_pcg = 0, t_rr = 0;
   bool timing = false;
   PcgTiming tm[2];  // [0] FP64 inner solves, [1] FP32 inner solves
@@ -74,7 +80,7 @@ struct Stats {
 
 // Small FP64 device workspace of one solve (sizes for m = 3b).
 struct Small {
-  DevBuf M, V, w, C, Ch, T1, T2, Rinv, cw, ew, sel, cnt, K, Z, th, Zs;
+  DevBuf M, V, w, C, Ch, T1, T2, Rinv, cw, ew, sel, cnt, K, Z, th, Zs, asel, Za;
   int mmax;
   Small(int b, hipStream_t s) {
     const int m = 3 * b;
@@ -96,6 +102,8 @@ struct Small {
     Z.reset(mm, s);
     th.reset(m * sizeof(double), s);
     Zs.reset(mm, s);
+    asel.reset((size_t)b * sizeof(int), s);
+    Za.reset((size_t)b * b * sizeof(double), s);
   }
 };
 
@@ -290,8 +298,22 @@ class Phase {
     MBL_HIP(hipStreamSynchronize(s_));
     res.resize(nev);
     for (int j = 0; j < nev; ++j) res[j] = std::sqrt(std::max(0.0, G[(size_t)j * nev + j]));
+    // soft locking: H-Ritz directions (columns of Z) of the wanted pairs
+    // below the locking tolerance, most converged first
+    locked_.clear();
+    if (p_.lock_tol > 0) {
+      std::vector<std::pair<double, int>> lk;
+      for (int j = 0; j < nev; ++j)
+        if (res[j] <= p_.lock_tol) lk.push_back({res[j], sel[j]});
+      std::sort(lk.begin(), lk.end());
+      for (const auto& e : lk) locked_.push_back(e.second);
+    }
     st_.t_rr += secs(t0);
   }
+
+  // Forget the locked set (every direction gets a new W column next step).
+  void unlock() { locked_.clear(); }
+  int nlocked() const { return (int)locked_.size(); }
 
   // One LOBPCG step: W from the residual, then RR on [X P W].
   // Returns false when no new direction survived (stagnation).
@@ -325,21 +347,54 @@ class Phase {
     }
     TB* W = S + b + bp_;
     const int64_t ld = B_.ld;
+    // Soft locking: wanted pairs already below the locking tolerance get no
+    // new direction.  R is rotated into the H-Ritz basis of span(X) (Z from
+    // check(); R Z is the residual block of those Ritz vectors up to a part
+    // inside span(X), which the orthogonalisation below removes), the locked
+    // columns are left out, and the active width is rounded up to whole
+    // 128-byte rows of the preconditioner's scalars, keeping the least
+    // converged locked pairs active, so the block CG keeps its tuned shapes.
+    int wq = b;
+    const TB* Rin = R;
+    int64_t ldRin = b;
+    if (p_.fold && m > 0 && !locked_.empty()) {
+      const int grain = 128 / (int)sizeof(TP);
+      int keep = b - (int)locked_.size();
+      keep = std::min(b, std::max(grain, (keep + grain - 1) / grain * grain));
+      if (keep < b) {
+        std::vector<char> drop(b, 0);
+        for (int k = 0; k < b - keep; ++k) drop[locked_[k]] = 1;
+        std::vector<int> act;
+        for (int j = 0; j < b; ++j)
+          if (!drop[j]) act.push_back(j);
+        MBL_HIP(hipMemcpyAsync(sm_.asel.get(), act.data(), keep * sizeof(int),
+                               hipMemcpyHostToDevice, s_));
+        gather_cols(b, keep, sm_.asel.as<int>(), sm_.Z.as<double>(), b, sm_.Za.as<double>(), keep,
+                    s_);
+        TB* Rt = B_.tmp.template as<TB>();
+        launch_combine<TB>(n, R, b, b, sm_.Za.as<double>(), keep, Rt, keep, keep, 0.0, s_);
+        MBL_HIP(hipStreamSynchronize(s_));  // act is a host temporary
+        Rin = Rt;
+        ldRin = keep;
+        wq = keep;
+      }
+    }
     if (p_.fold && m > 0) {
       const auto t0 = clk::now();
       PcgTiming* tm = st_.timing ? &st_.tm[sizeof(TP) == 4 ? 1 : 0] : nullptr;
       if constexpr (std::is_same<TB, TP>::value) {
-        run_pcg<TP>(H_, p_.sigma, jac, R, b, W, ld, b, m, s_, tm);
+        run_pcg<TP>(H_, p_.sigma, jac, Rin, ldRin, W, ld, wq, m, s_, tm);
         MBL_HIP(hipStreamSynchronize(s_));
       } else {
-        DevBuf rp((size_t)n * b * sizeof(TP), s_), wp((size_t)n * b * sizeof(TP), s_);
-        launch_convert<TB, TP>(n, b, R, b, rp.as<TP>(), b, s_);
-        run_pcg<TP>(H_, p_.sigma, jac, rp.as<TP>(), b, wp.as<TP>(), b, b, m, s_, tm);
-        launch_convert<TP, TB>(n, b, wp.as<TP>(), b, W, ld, s_);
+        DevBuf rp((size_t)n * wq * sizeof(TP), s_), wp((size_t)n * wq * sizeof(TP), s_);
+        launch_convert<TB, TP>(n, wq, Rin, ldRin, rp.as<TP>(), wq, s_);
+        run_pcg<TP>(H_, p_.sigma, jac, rp.as<TP>(), wq, wp.as<TP>(), wq, wq, m, s_, tm);
+        launch_convert<TP, TB>(n, wq, wp.as<TP>(), wq, W, ld, s_);
         MBL_HIP(hipStreamSynchronize(s_));
       }
       st_.applies += 2LL * m;
       st_.pcg_steps += m;
+      st_.pcg_columns += (int64_t)m * wq;
       st_.t_pcg += secs(t0);
     } else if constexpr (std::is_same<TB, double>::value) {
       if (!p_.fold && p_.diag_precond) {
@@ -358,12 +413,12 @@ class Phase {
     // orthogonalise W against [X P] twice, then Cholesky-QR twice
     const int xp = b + bp_;
     for (int pass = 0; pass < 2; ++pass) {
-      launch_gram<TB>(n, S, ld, xp, W, ld, b, sm_.T1.as<double>(), b, s_);
-      small_gemm(xp, b, 0, 0.0, sm_.T1.as<double>(), b, false, sm_.T1.as<double>(), b, false,
-                 -1.0, sm_.T1.as<double>(), b, s_);  // negate
-      launch_combine<TB>(n, S, ld, xp, sm_.T1.as<double>(), b, W, ld, b, 1.0, s_);
+      launch_gram<TB>(n, S, ld, xp, W, ld, wq, sm_.T1.as<double>(), wq, s_);
+      small_gemm(xp, wq, 0, 0.0, sm_.T1.as<double>(), wq, false, sm_.T1.as<double>(), wq, false,
+                 -1.0, sm_.T1.as<double>(), wq, s_);  // negate
+      launch_combine<TB>(n, S, ld, xp, sm_.T1.as<double>(), wq, W, ld, wq, 1.0, s_);
     }
-    const int bw = cholqr2(W, ld, b);
+    const int bw = cholqr2(W, ld, wq);
     st_.t_rr += secs(t0);
     if (bw == 0) return false;
     apply(W, ld, HS + b + bp_, ld, bw);
@@ -400,6 +455,7 @@ class Phase {
   int cur_ = 0;
   int bp_ = 0;
   std::vector<double> mu_;
+  std::vector<int> locked_;  // Z columns of locked wanted pairs, most converged first
 };
 
 // Fresh FP64 residuals of V (n x nev) with values theta (of H - sigma).
@@ -445,9 +501,14 @@ bool run_phase(Phase<TB>& ph, const TP* jac, const Params& p, double stop_tol, i
   while (true) {
     ph.check(theta, res);
     const double r = maxv(res);
-    if (p.verbose)
-      std::fprintf(stderr, "[mbl %s] iter %d applies %lld max_resid %.3e\n", tag, st.iters,
-                   (long long)st.applies, r);
+    if (p.verbose) {
+      if (p.lock_tol > 0)
+        std::fprintf(stderr, "[mbl %s] iter %d applies %lld max_resid %.3e locked %d\n", tag,
+                     st.iters, (long long)st.applies, r, ph.nlocked());
+      else
+        std::fprintf(stderr, "[mbl %s] iter %d applies %lld max_resid %.3e\n", tag, st.iters,
+                     (long long)st.applies, r);
+    }
     if (r <= stop_tol) return true;
     if (patience > 0) {
       if (r < gain * best) {
@@ -480,6 +541,7 @@ mbl_status solve_interior(const Ham& H, double sigma, int nev, int b, double tol
   p.pcg_iters = o.pcg_iters > 0 ? o.pcg_iters : default_pcg_iters(H.n);
   p.verbose = o.verbose;
   p.seed = o.seed;
+  p.lock_tol = o.lock ? 0.1 * tol : 0.0;
   Stats st;
   st.timing = o.timing != 0;
   Small sm(b, s);
@@ -537,7 +599,9 @@ mbl_status solve_interior(const Ham& H, double sigma, int nev, int b, double tol
       res = fresh_residuals(H, sigma, V.as<double>(), nev, nev, theta, st, s);
       ok = reached && maxv(res) <= tol;
       if (ok || !reached || iters_left <= 0) break;
-      // tracked residuals passed but fresh ones did not: one more step
+      // tracked residuals passed but fresh ones did not: one more step, with
+      // every direction active
+      ph.unlock();
       --iters_left;
       ++st.iters;
       bool stepped;
@@ -563,6 +627,7 @@ mbl_status solve_interior(const Ham& H, double sigma, int nev, int b, double tol
     info->iters_fp64 = st.iters_fp64;
     info->applies = st.applies;
     info->pcg_steps = st.pcg_steps;
+    info->pcg_columns = st.pcg_columns;
     info->t_pcg = st.t_pcg;
     info->t_rr = st.t_rr;
     info->max_resid = maxv(res);

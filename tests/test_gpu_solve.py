@@ -124,3 +124,44 @@ def test_solve_is_deterministic():
     a = H.solve(0.1, 4, 8, tol=1e-10)
     b = H.solve(0.1, 4, 8, tol=1e-10)
     assert np.array_equal(a[0], b[0]) and torch.equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("precision", ["f64", "mixed"])
+def test_soft_locking_dense_parity(precision):
+    """Soft locking (opts.lock): the same pairs as dense diagonalisation, and the
+    inner CG ran on fewer columns than block x steps once pairs locked; without
+    the option every CG step covers the whole block."""
+    L, nev, b = 14, 32, 48
+    h = workloads.disorder(L, 4.0, 0)
+    st, Ho = hamiltonian.sector_matrix(L, L // 2, 1.0, 1.0, h)
+    emin, emax = spectrum.bounds(Ho)
+    sigma = spectrum.shift_from_density(emin, emax, 0.5)
+    w_ref, V_ref = spectrum.nearest(Ho, sigma, nev)
+    H = api.Hamiltonian(L, h)
+    ev, V, rs, info = H.solve(sigma, nev, b, tol=1e-10, precision=precision, lock=True)
+    assert info["status"] == "MBL_OK"
+    _check(Ho, sigma, nev, ev, V, rs, w_ref, V_ref)
+    assert info["pcg_columns"] < info["pcg_steps"] * b, info
+    ev0, V0, rs0, info0 = H.solve(sigma, nev, b, tol=1e-10, precision=precision)
+    assert info0["pcg_columns"] == info0["pcg_steps"] * b
+    _check(Ho, sigma, nev, ev0, V0, rs0, w_ref, V_ref)
+
+
+def test_soft_locking_delta_zero_l18():
+    """Soft locking on a larger sector (L = 18, n = 48620, 32 pairs, block 48) at
+    Delta = 0, against the exact single-particle subset sums.  Short inner
+    solves (60 CG steps) spread the pairs' convergence over many outer
+    iterations, so pairs lock well before the last one converges."""
+    L, nev, b = 18, 32, 48
+    h = workloads.disorder(L, 4.0, 0)
+    st = basis.enumerate_sector(L, L // 2)
+    e_all = freefermion.energies(L, L // 2, 1.0, h, st)
+    sigma = spectrum.shift_from_density(e_all.min(), e_all.max(), 0.5)
+    e_ref, _ = freefermion.nearest(L, L // 2, 1.0, h, st, sigma, nev)
+    H = api.Hamiltonian(L, h, Delta=0.0)
+    ev, V, rs, info = H.solve(sigma, nev, b, tol=1e-10, lock=True, pcg_iters=60)
+    assert info["status"] == "MBL_OK"
+    _, Ho = hamiltonian.sector_matrix(L, L // 2, 1.0, 0.0, h, states=st)
+    assert np.all(linalg.residual_norms(Ho, ev, V.cpu().numpy()) <= 1e-10)
+    np.testing.assert_allclose(ev, e_ref, atol=1e-10)
+    assert info["pcg_columns"] < info["pcg_steps"] * b, info
