@@ -134,7 +134,20 @@ def cpu_baseline(wl, gpu_runs, verbose=False):
                    f"core, projected with the GPU solve's {run['pcg_steps']} CG steps and "
                    f"{other_applies} other applies: {t_proj:.0f} s for {nev} pairs"),
         "cpu_checked_pairs": verified,
+        "host_cpu": _cpu_model(),
+        "host_cores_available": len(os.sched_getaffinity(0)),
     }
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def run_batch(args):
@@ -477,6 +490,20 @@ def main():
     torch.cuda.synchronize()
     hx_cache_gbps = 2 * n * wl["block"] * s / (e0.elapsed_time(e1) / reps * 1e-3) / 1e9
     del Xs, Ys
+    # the streaming-copy rate of this GPU (1 GiB read + 1 GiB written per copy),
+    # the practical counterpart of the published HBM peak
+    src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbps = 2 * src.numel() * 4 / (e0.elapsed_time(e1) / 5 * 1e-3) / 1e9
+    del src, dst
+    roofline["measured_copy_GBps"] = round(copy_gbps, 1)
 
     last = runs[-1]
     per_w = {str(W): {"sigma": sigmas[W], "iters": r["info"]["iters"],
