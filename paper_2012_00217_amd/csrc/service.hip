@@ -163,6 +163,7 @@ mbl_status batch_solve(int count, const mbl_problem* probs, mbl_result* res, int
       run_problem(*jobs[i], res[i].evecs_dev, res[i].ldv, s);
       jobs[i]->r.latency = std::chrono::duration<double>(clk::now() - t0).count();
       copy_out(*jobs[i], &res[i]);
+      jobs[i]->done = true;
     }
     (void)hipStreamSynchronize(s);
     (void)hipStreamDestroy(s);
@@ -171,6 +172,9 @@ mbl_status batch_solve(int count, const mbl_problem* probs, mbl_result* res, int
   const int nt = std::max(1, std::min(conc, count));
   for (int t = 0; t < nt; ++t) pool.emplace_back(worker);
   for (auto& t : pool) t.join();
+  // a problem no worker reached (every worker failed to create its stream)
+  for (int i = 0; i < count; ++i)
+    if (!jobs[i]->done) res[i].status = MBL_EDEVICE;
   mbl_status first = MBL_OK;
   for (int i = 0; i < count && first == MBL_OK; ++i)
     if (res[i].status != MBL_OK) first = (mbl_status)res[i].status;
@@ -307,13 +311,17 @@ mbl_status server_wait(Server* srv, uint64_t ticket, double timeout_s, mbl_resul
     return MBL_ETIMEOUT;
   }
   copy_out(*j, out);
-  if (out->evecs_dev && j->V.get() && j->n > 0) {
-    MBL_HIP(hipMemcpy2DAsync(out->evecs_dev, out->ldv * sizeof(double), j->V.get(),
-                             j->p.nev * sizeof(double), j->p.nev * sizeof(double), j->n,
+  // take the job out of the table, then copy its vectors without holding the
+  // lock (workers finishing other jobs need it)
+  std::unique_ptr<Job> own = std::move(it->second);
+  srv->jobs.erase(it);
+  lk.unlock();
+  if (out->evecs_dev && own->V.get() && own->n > 0) {
+    MBL_HIP(hipMemcpy2DAsync(out->evecs_dev, out->ldv * sizeof(double), own->V.get(),
+                             own->p.nev * sizeof(double), own->p.nev * sizeof(double), own->n,
                              hipMemcpyDeviceToDevice, srv->copy));
     MBL_HIP(hipStreamSynchronize(srv->copy));
   }
-  srv->jobs.erase(it);
   return MBL_OK;
 }
 
