@@ -92,3 +92,9 @@ def test_sz_to_nup():
     for bad in [(13, 0), (12, 0.5), (4, 3)]:
         with pytest.raises(ValueError):
             basis.nup_from_sz(*bad)
+
+
+def test_bits_are_site_occupations():
+    """Site i is bit i (U2): hand-written occupations of three 4-site states."""
+    b = basis.bits([0b0101, 0b0011, 0b1000], 4)
+    assert b.tolist() == [[1, 0, 1, 0], [1, 1, 0, 0], [0, 0, 0, 1]]

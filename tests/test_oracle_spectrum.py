@@ -134,3 +134,10 @@ def test_cholqr_and_angles():
     V = U.copy()
     V[:, 3] = sla.null_space(U.T)[:, 0]
     assert abs(linalg.max_cluster_angle(ev, U, V, 1e-8) - np.pi / 2) < 1e-7
+
+
+def test_clusters_group_near_degenerate_levels():
+    """Neighbouring eigenvalues closer than tol share a cluster; others do not."""
+    ev = np.array([0.0, 1e-12, 1.0, 2.0, 2.0 + 5e-10, 2.0 + 1e-9, 3.0])
+    assert linalg.clusters(ev, 1e-9) == [[0, 1], [2], [3, 4, 5], [6]]
+    assert linalg.clusters(ev, 1e-13) == [[0], [1], [2], [3], [4], [5], [6]]
