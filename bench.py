@@ -360,7 +360,8 @@ def main():
         args.count = 40 if args.workload == "serve" else 256
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
+              "(the library solves on one GPU; sharding one solve over several GPUs is not "
+              "implemented)", file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "batch":
