@@ -22,7 +22,7 @@ def test_more_than_one_gpu_is_refused_with_a_message():
 def test_help_lists_the_workloads():
     r = _run("--help")
     assert r.returncode == 0
-    for w in ("l20", "l24", "l12", "batch", "serve", "gram"):
+    for w in ("l20", "l24", "l12", "batch", "serve", "gram", "slices"):
         assert w in r.stdout
 
 
