@@ -150,6 +150,8 @@ void launch_combine(int64_t n, const T* A, int64_t lda, int p, const double* C, 
                     int64_t ldy, int q, double beta, hipStream_t s);
 
 // Small dense (single workgroup) FP64 kernels; matrices row-major.
+// small_eigh: ascending eigenvalues w and eigenvectors V (columns) of the
+// symmetric A; V == nullptr asks for eigenvalues only (m <= 128).
 void small_eigh(int m, const double* A, int64_t lda, double* w, double* V, int64_t ldv,
                 double* work, hipStream_t s);
 

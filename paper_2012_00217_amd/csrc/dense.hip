@@ -6,7 +6,8 @@
 //    split into disjoint pairs, so all rotations of a round commute and the
 //    matrix splits into 2 x 2 blocks that are updated independently,
 //    A_kl <- J_k^T A_kl J_l.  Sizes <= 96 run in one workgroup with A and V in
-//    LDS; larger ones run one kernel per round, ping-ponging A between two
+//    LDS (<= 128 when only eigenvalues are wanted, with A alone in LDS); larger
+//    ones run one kernel per round, ping-ponging A between two
 //    buffers so the rotations of a round are computed from the unmodified
 //    matrix.  A sweep ends with a count of rotations; none means converged.
 //    Jacobi keeps small eigenvalues of positive semi-definite matrices to
@@ -64,10 +65,13 @@ __device__ inline void rot_block(double ck, double sk, double cl, double sl, dou
   bqq = sl * rqp + cl * rqq;
 }
 
-// Whole Jacobi eigensolver in one workgroup; A, V in LDS (mm even, mm <= 96).
+// Whole Jacobi eigensolver in one workgroup (mm even): A and V in LDS for
+// mm <= 96, or A alone when only eigenvalues are wanted (kVec false, mm <= 128).
 // The pairs of a round are tabulated once per round, and every thread keeps a
 // fixed pair column l (and walks rows k, or matrix rows i, with a fixed stride),
 // so the inner loops do no integer division.
+constexpr int kLdsPairs = 64;  // pairs per round, mm / 2 <= 64
+template <bool kVec>
 __global__ __launch_bounds__(1024) void k_jacobi_lds(int m, const double* __restrict__ A,
                                                      int64_t lda, double* __restrict__ w,
                                                      double* __restrict__ V, int64_t ldv,
@@ -75,15 +79,15 @@ __global__ __launch_bounds__(1024) void k_jacobi_lds(int m, const double* __rest
   extern __shared__ double sh[];
   const int mm = m + (m & 1);
   double* a = sh;             // mm x mm
-  double* v = sh + mm * mm;   // mm x mm
-  __shared__ double cs_c[48], cs_s[48];
-  __shared__ int pp[48], qq[48];
+  double* v = sh + mm * mm;   // mm x mm (kVec only)
+  __shared__ double cs_c[kLdsPairs], cs_s[kLdsPairs];
+  __shared__ int pp[kLdsPairs], qq[kLdsPairs];
   __shared__ int nrot;
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int e = tid; e < mm * mm; e += nt) {
     const int i = e / mm, j = e % mm;
     a[e] = (i < m && j < m) ? A[(int64_t)i * lda + j] : 0.0;
-    v[e] = (i == j) ? 1.0 : 0.0;
+    if constexpr (kVec) v[e] = (i == j) ? 1.0 : 0.0;
   }
   // symmetrise from the upper triangle
   __syncthreads();
@@ -128,10 +132,12 @@ __global__ __launch_bounds__(1024) void k_jacobi_lds(int m, const double* __rest
           a[qk * mm + pl] = bqp;
           a[qk * mm + ql] = bqq;
         }
-        for (int i = r0; i < mm; i += rows_per_pass) {
-          const double vp = v[i * mm + pl], vq = v[i * mm + ql];
-          v[i * mm + pl] = cl * vp - sl * vq;
-          v[i * mm + ql] = sl * vp + cl * vq;
+        if constexpr (kVec) {
+          for (int i = r0; i < mm; i += rows_per_pass) {
+            const double vp = v[i * mm + pl], vq = v[i * mm + ql];
+            v[i * mm + pl] = cl * vp - sl * vq;
+            v[i * mm + ql] = sl * vp + cl * vq;
+          }
         }
       }
       __syncthreads();
@@ -149,7 +155,8 @@ __global__ __launch_bounds__(1024) void k_jacobi_lds(int m, const double* __rest
       r += (di < dj) || (di == dj && i < j);
     }
     w[r] = dj;
-    for (int i = 0; i < m; ++i) V[(int64_t)i * ldv + r] = v[i * mm + j];
+    if constexpr (kVec)
+      for (int i = 0; i < m; ++i) V[(int64_t)i * ldv + r] = v[i * mm + j];
   }
 }
 
@@ -372,16 +379,29 @@ void small_eigh(int m, const double* A, int64_t lda, double* w, double* V, int64
   const int max_sweeps = 30;
   if (m == 1) {
     MBL_HIP(hipMemcpyAsync(w, A, sizeof(double), hipMemcpyDeviceToDevice, s));
-    const double one = 1.0;
-    MBL_HIP(hipMemcpyAsync(V, &one, sizeof(double), hipMemcpyHostToDevice, s));
-    MBL_HIP(hipStreamSynchronize(s));
+    if (V) {
+      const double one = 1.0;
+      MBL_HIP(hipMemcpyAsync(V, &one, sizeof(double), hipMemcpyHostToDevice, s));
+      MBL_HIP(hipStreamSynchronize(s));
+    }
     return;
   }
+  if (!V && mm <= 2 * kLdsPairs) {
+    // eigenvalues only: A alone in LDS
+    const size_t shm = (size_t)mm * mm * sizeof(double);
+    MBL_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_jacobi_lds<false>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+    hipLaunchKernelGGL(k_jacobi_lds<false>, dim3(1), dim3(1024), shm, s, m, A, lda, w,
+                       (double*)nullptr, (int64_t)0, max_sweeps);
+    MBL_CHECK_LAUNCH();
+    return;
+  }
+  if (!V) fail(MBL_EINTERNAL, "small_eigh: eigenvectors are needed above 128");
   if (mm <= 96) {
     const size_t shm = (size_t)2 * mm * mm * sizeof(double);
-    MBL_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_jacobi_lds),
+    MBL_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_jacobi_lds<true>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
-    hipLaunchKernelGGL(k_jacobi_lds, dim3(1), dim3(1024), shm, s, m, A, lda, w, V, ldv,
+    hipLaunchKernelGGL(k_jacobi_lds<true>, dim3(1), dim3(1024), shm, s, m, A, lda, w, V, ldv,
                        max_sweeps);
     MBL_CHECK_LAUNCH();
     return;

@@ -74,8 +74,9 @@ void entanglement_entropy(const Ham& H, const double* V, int64_t ldv, int nev, i
       hipLaunchKernelGGL(k_seg_gram, dim3((unsigned)(((int64_t)dim * dim + 255) / 256)), dim3(256),
                          0, s, V + j, ldv, st.as<int64_t>(), c, a, (int)by_rows, G.as<double>());
       MBL_CHECK_LAUNCH();
-      small_eigh(dim, G.as<double>(), dim, w.as<double>(), Z.as<double>(), dim,
-                 work.as<double>(), s);
+      // only the eigenvalues are needed: blocks up to 128 take the values-only path
+      double* zv = dim + (dim & 1) <= 128 ? nullptr : Z.as<double>();
+      small_eigh(dim, G.as<double>(), dim, w.as<double>(), zv, dim, work.as<double>(), s);
       MBL_HIP(hipMemcpyAsync(p.data(), w.get(), dim * sizeof(double), hipMemcpyDeviceToHost, s));
       MBL_HIP(hipStreamSynchronize(s));
       for (double x : p)

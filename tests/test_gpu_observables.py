@@ -84,3 +84,17 @@ def test_entropy_at_full_size_l20():
         S = H.entanglement_entropy(V, cut)
         want = [observables.entanglement_entropy(Vn[:, j], st, L, cut) for j in range(6)]
         np.testing.assert_allclose(S, want, atol=1e-9)
+
+
+@pytest.mark.parametrize("L,cut", [(16, 8), (18, 9), (18, 5)])
+def test_entropy_of_random_vectors(L, cut):
+    """Random unit vectors at sizes whose reduced-density blocks reach the
+    small eigensolver's one-workgroup limits (70 at L=16, 126 at L=18 cut 9),
+    against the oracle's SVD of the full 2^L vector."""
+    st = basis.enumerate_sector(L, L // 2)
+    V = workloads.random_block(len(st), 3, seed=L + cut)
+    V /= np.linalg.norm(V, axis=0)
+    H = api.Hamiltonian(L, workloads.disorder(L, 1.0, 0))
+    S = H.entanglement_entropy(torch.from_numpy(V).cuda(), cut)
+    want = [observables.entanglement_entropy(V[:, j], st, L, cut) for j in range(3)]
+    np.testing.assert_allclose(S, want, atol=1e-10)
