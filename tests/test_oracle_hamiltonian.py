@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 
 from oracle import basis, hamiltonian, freefermion
+from paper_2012_00217_amd import workloads
 
 SX = np.array([[0, 1], [1, 0]], dtype=complex) / 2
 SY = np.array([[0, 1j], [-1j, 0]], dtype=complex) / 2  # basis (down, up) = (bit 0, bit 1)
@@ -183,3 +184,19 @@ def test_fold_diagonal_matches_dense_square_and_closed_form():
     np.testing.assert_allclose(d, np.diag(Hd @ Hd), rtol=1e-14)
     nd = np.bitwise_count((st ^ (st >> np.uint64(1))) & np.uint64((1 << (L - 1)) - 1)).astype(float)
     np.testing.assert_allclose(d, (H.diagonal() - sigma) ** 2 + (J / 2) ** 2 * nd, rtol=1e-13)
+
+
+def test_trace_closed_form_in_every_sector():
+    """trace(H) over the sector with k up spins, from counting k-subsets: each of
+    the L-1 bonds gives n [k(k-1)/(L(L-1)) - k/L + 1/4] J Delta, each field gives
+    n (k/L - 1/2) h_i.  Pins the diagonal and the assembled matrix at any k."""
+    for L in (5, 8, 11):
+        for k in range(L + 1):
+            h = workloads.disorder(L, 2.5, 31 * L + k)
+            J, D = 0.7, 1.3
+            st, Hs = hamiltonian.sector_matrix(L, k, J, D, h)
+            n = len(st)
+            pair = k * (k - 1) / (L * (L - 1)) - k / L + 0.25
+            want = J * D * (L - 1) * n * pair + n * (k / L - 0.5) * h.sum()
+            assert hamiltonian.diagonal(L, st, J, D, h).sum() == pytest.approx(want, abs=1e-9)
+            assert Hs.diagonal().sum() == pytest.approx(want, abs=1e-9)
