@@ -113,7 +113,12 @@ mbl_status mbl_diagonal(mbl_ham H, double sigma, double* diag_dev,
  * not overlap.  Async.  The launch schedule comes from the library's table of
  * tuned schedules (nearest sector size, same row width); the environment
  * variables MBL_APPLY_CHUNK_BYTES, MBL_APPLY_LANE_BYTES, MBL_APPLY_XCD_GROUP and
- * MBL_APPLY_SLOTS_PER_XCD override its fields (they also apply to mbl_pcg). */
+ * MBL_APPLY_SLOTS_PER_XCD override its fields (they also apply to mbl_pcg).
+ * MBL_APPLY_SPLIT=1 selects the two-pass kernel instead (the chain cut in two
+ * halves, each half's flips gathered from an LDS tile; also used by mbl_pcg
+ * and the solvers); MBL_SPLIT_PANEL_BYTES and MBL_SPLIT_SLOTS override its
+ * column-panel width and workgroups per XCD.  Both kernels compute the same
+ * sums in different orders. */
 mbl_status mbl_apply_block(mbl_ham H, double sigma, mbl_precision prec,
                            const void* X, int64_t ldx, void* Y, int64_t ldy,
                            int b, hipStream_t stream);

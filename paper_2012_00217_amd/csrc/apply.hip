@@ -643,6 +643,7 @@ template <class T>
 void launch_apply(const Ham& H, double sigma, const T* X, int64_t ldx, T* Y, int64_t ldy, int w,
                   hipStream_t s) {
   if (H.n == 0 || w == 0) return;
+  if (split_apply<T>(H, sigma, X, ldx, Y, ldy, w, s)) return;
   const bool aligned = al16(X, ldx, sizeof(T)) && al16(Y, ldy, sizeof(T));
   ApplyArgs<T> a = base_args<T>(H, sigma);
   a.X = X;
@@ -690,6 +691,136 @@ int pcg_chunk_width(int64_t n, int b) {
   return w;
 }
 
+// Replays `step` m - it times: from a hipGraph captured on a private
+// non-blocking stream (forked from and joined back to s by events) when at
+// least 8 steps remain, else launch by launch.  The legacy default stream
+// cannot be captured, and a capture on a caller's blocking stream would forbid
+// legacy-stream work in every other thread of the process meanwhile.
+template <class F>
+void replay_steps(F&& step, int it, int m, hipStream_t& s) {
+  if (env_int("MBL_PCG_GRAPH", 1) != 0 && m - it >= 8) {
+    hipStream_t own = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+    MBL_HIP(hipStreamCreateWithFlags(&own, hipStreamNonBlocking));
+    hipError_t err = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+    if (err == hipSuccess) err = hipEventCreateWithFlags(&join, hipEventDisableTiming);
+    if (err == hipSuccess) err = hipEventRecord(fork, s);
+    if (err == hipSuccess) err = hipStreamWaitEvent(own, fork, 0);
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    if (err == hipSuccess) err = hipStreamBeginCapture(own, hipStreamCaptureModeThreadLocal);
+    if (err == hipSuccess) {
+      const hipStream_t keep = s;
+      s = own;  // step() launches on s
+      try {
+        step();
+      } catch (...) {
+        s = keep;
+        hipGraph_t dropped = nullptr;
+        (void)hipStreamEndCapture(own, &dropped);
+        if (dropped) (void)hipGraphDestroy(dropped);
+        (void)hipStreamSynchronize(own);
+        (void)hipStreamDestroy(own);
+        (void)hipEventDestroy(fork);
+        (void)hipEventDestroy(join);
+        throw;
+      }
+      s = keep;
+      err = hipStreamEndCapture(own, &graph);
+    }
+    if (err == hipSuccess) err = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    for (; err == hipSuccess && it < m; ++it) err = hipGraphLaunch(exec, own);
+    if (err == hipSuccess) err = hipEventRecord(join, own);
+    if (err == hipSuccess) err = hipStreamWaitEvent(s, join, 0);
+    // the graph and its stream are torn down only after the replays finished
+    const hipError_t se = hipStreamSynchronize(own);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipStreamDestroy(own);
+    if (fork) (void)hipEventDestroy(fork);
+    if (join) (void)hipEventDestroy(join);
+    MBL_HIP(err);
+    MBL_HIP(se);
+  }
+  for (; it < m; ++it) step();
+}
+
+// Block PCG of one column chunk through the split (two-pass) kernels:
+//   init: r = R, x = 0, p = M^-1 r, rho = r.M^-1 r   (beta = 0)
+//   step: [p = M^-1 r + beta p; T = (H - sigma) p; |T|^2] -> alpha
+//         [q = (H - sigma) T; x += alpha p; r -= alpha q; r.M^-1 r] -> beta
+// The p-update of each step is fused into the first apply of the next, which
+// with beta = 0 after init reproduces p = M^-1 r.
+template <class T>
+void run_pcg_split(const Ham& H, double sigma, const T* jac, const T* Rc, int64_t ldr,
+                   const SplitCg<T>& sg, int m, bool aligned, const Sched& sc, hipStream_t s,
+                   PcgTiming* tm) {
+  const int64_t n = H.n;
+  const int w = sg.w;
+  for (const Chunk& ch : plan_chunks<T>(w, aligned, sc)) {
+    const Grid g = make_grid(n, ch.log2G, sc);
+    EltArgs<T> e{};
+    e.R = Rc;
+    e.ldR = ldr;
+    e.x = sg.x;
+    e.ldxv = sg.ldx;
+    e.r = sg.r;
+    e.ldr = sg.ldr;
+    e.p = sg.p;
+    e.ldp = sg.ldp;
+    e.jac = jac;
+    e.coef = sg.coef;
+    e.part = sg.part;
+    e.n = n;
+    dispatch_elt<T, ELT_INIT>(ch, g, e, s);
+    finalize<FIN_INIT>(ch, g, sg.part, const_cast<PcgCoef*>(sg.coef), s);
+  }
+  auto fin = [&](int nwp, auto mode, hipStream_t st) {
+    hipLaunchKernelGGL(k_pcg_finalize<decltype(mode)::value>, dim3(w), dim3(kThreads), 0, st,
+                       sg.part, nwp, w, 0, const_cast<PcgCoef*>(sg.coef));
+    MBL_CHECK_LAUNCH();
+  };
+  using FA = std::integral_constant<int, FIN_ALPHA>;
+  using FB = std::integral_constant<int, FIN_BETA>;
+  const int ntimed = tm ? std::min(m, PcgTiming::kSample) : 0;
+  if (tm) tm->init();
+  int it = 0;
+  for (; it < ntimed; ++it) {
+    MBL_HIP(hipEventRecord(tm->ev[4 * it + 0], s));
+    int nwp = split_cg_apply<T>(H, sigma, 0, sg, s);
+    MBL_HIP(hipEventRecord(tm->ev[4 * it + 1], s));
+    fin(nwp, FA{}, s);
+    MBL_HIP(hipEventRecord(tm->ev[4 * it + 2], s));
+    nwp = split_cg_apply<T>(H, sigma, 1, sg, s);
+    MBL_HIP(hipEventRecord(tm->ev[4 * it + 3], s));
+    fin(nwp, FB{}, s);
+  }
+  auto step = [&]() {
+    const int nwp1 = split_cg_apply<T>(H, sigma, 0, sg, s);
+    fin(nwp1, FA{}, s);
+    const int nwp2 = split_cg_apply<T>(H, sigma, 1, sg, s);
+    fin(nwp2, FB{}, s);
+  };
+  replay_steps(step, it, m, s);
+  if (ntimed > 0) {
+    MBL_HIP(hipStreamSynchronize(s));
+    for (int k = 0; k < ntimed; ++k) {
+      float ta = 0.f, tc = 0.f;
+      MBL_HIP(hipEventElapsedTime(&ta, tm->ev[4 * k + 0], tm->ev[4 * k + 1]));
+      MBL_HIP(hipEventElapsedTime(&tc, tm->ev[4 * k + 2], tm->ev[4 * k + 3]));
+      tm->ms[0] += ta;
+      tm->ms[1] += tc;
+    }
+    tm->launches[0] += ntimed;
+    tm->launches[1] += ntimed;
+    // algorithmic bytes: apply1 (p-update fused) reads r, p and writes p, T;
+    // apply2 reads T, p, x, r and writes x, r
+    tm->bytes[0] += (double)ntimed * 4.0 * n * w * sizeof(T);
+    tm->bytes[1] += (double)ntimed * 6.0 * n * w * sizeof(T);
+    tm->split = true;
+  }
+}
+
 template <class T>
 void run_pcg(const Ham& H, double sigma, const T* jac, const T* R, int64_t ldr, T* W, int64_t ldw,
              int b, int m, hipStream_t s, PcgTiming* tm) {
@@ -715,6 +846,14 @@ void run_pcg(const Ham& H, double sigma, const T* jac, const T* R, int64_t ldr, 
     PcgCoef* cf = coef + c0;
     const bool aligned = al16(Rc, ldr, sizeof(T)) && al16(x, ldx, sizeof(T)) && al16(r, w, sizeof(T));
     const Sched sc = sched_for(H, w * (int)sizeof(T), (int)sizeof(T));
+    SplitCg<T> sg{x, ldx, r, w, p, w, t, w, cf, part.as<double>(), w};
+    if (split_cg_ready<T>(H, sg)) {
+      run_pcg_split<T>(H, sigma, jac, Rc, ldr, sg, m, aligned, sc, s, tm);
+      if (wc < b)
+        MBL_HIP(hipMemcpy2DAsync(W + c0, ldw * sizeof(T), x, w * sizeof(T), w * sizeof(T), n,
+                                 hipMemcpyDeviceToDevice, s));
+      continue;
+    }
     for (const Chunk& ch : plan_chunks<T>(w, aligned, sc)) {
       if ((size_t)ch.w * kMaxWg * sizeof(double) > part.bytes()) fail(MBL_EINTERNAL, "pcg: part");
       const Grid g = make_grid(n, ch.log2G, sc);
@@ -775,63 +914,7 @@ void run_pcg(const Ham& H, double sigma, const T* jac, const T* R, int64_t ldr, 
       }
       // The remaining steps replay one captured step: every CG coefficient
       // lives on the device, so the five launches are identical each step.
-      if (env_int("MBL_PCG_GRAPH", 1) != 0 && m - it >= 8) {
-        // capture on a private non-blocking stream (ordered after s by an
-        // event, joined back afterwards): the legacy default stream cannot be
-        // captured, and a capture on a caller's blocking stream would forbid
-        // legacy-stream work in every other thread of the process meanwhile
-        hipStream_t cs = s, own = nullptr;
-        hipEvent_t fork = nullptr, join = nullptr;
-        {
-          MBL_HIP(hipStreamCreateWithFlags(&own, hipStreamNonBlocking));
-          MBL_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
-          MBL_HIP(hipEventCreateWithFlags(&join, hipEventDisableTiming));
-          MBL_HIP(hipEventRecord(fork, s));
-          MBL_HIP(hipStreamWaitEvent(own, fork, 0));
-          cs = own;
-        }
-        hipGraph_t graph = nullptr;
-        hipGraphExec_t exec = nullptr;
-        hipError_t err = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-        if (err == hipSuccess) {
-          const hipStream_t keep = s;
-          s = cs;  // step() launches on s
-          try {
-            step();
-          } catch (...) {
-            s = keep;
-            hipGraph_t dropped = nullptr;
-            (void)hipStreamEndCapture(cs, &dropped);
-            if (dropped) (void)hipGraphDestroy(dropped);
-            if (own) {
-              (void)hipStreamSynchronize(own);
-              (void)hipStreamDestroy(own);
-              (void)hipEventDestroy(fork);
-              (void)hipEventDestroy(join);
-            }
-            throw;
-          }
-          s = keep;
-          err = hipStreamEndCapture(cs, &graph);
-        }
-        if (err == hipSuccess) err = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        for (; err == hipSuccess && it < m; ++it) err = hipGraphLaunch(exec, cs);
-        if (own && err == hipSuccess) {
-          err = hipEventRecord(join, own);
-          if (err == hipSuccess) err = hipStreamWaitEvent(s, join, 0);
-        }
-        const hipError_t se = hipStreamSynchronize(cs);
-        if (exec) (void)hipGraphExecDestroy(exec);
-        if (graph) (void)hipGraphDestroy(graph);
-        if (own) {
-          (void)hipStreamDestroy(own);
-          (void)hipEventDestroy(fork);
-          (void)hipEventDestroy(join);
-        }
-        MBL_HIP(err);
-        MBL_HIP(se);
-      }
-      for (; it < m; ++it) step();
+      replay_steps(step, it, m, s);
       if (ntimed > 0) {
         MBL_HIP(hipStreamSynchronize(s));
         for (int it = 0; it < ntimed; ++it) {

@@ -87,6 +87,47 @@ class DevBuf {
   bool ordered_ = true;
 };
 
+// One tile of the two-pass (split) apply.  The chain is cut between sites q-1
+// and q; a state is s = (hi << q) | lo.  In row order (ascending s) the rows
+// with one fixed hi form a contiguous block, indexed by the colex rank of lo
+// among the q-site configurations with the same number of up spins.
+//   low pass : tile = one block (fixed hi); row0 = first row, code = hi,
+//              aux = index of the block's first lo configuration in lo_states.
+//   high pass: tile = one lo configuration and every hi it combines with;
+//              row0 = colex rank j of lo, code = lo, aux = index of the first
+//              hi configuration in hi_states / hoff.
+// code and the *_info tables pack a configuration as value | (nd << 24), nd
+// being its number of anti-aligned bonds inside the half.  E is the energy of
+// the half (ZZ of its inner bonds and its fields); for the tile it is the
+// energy of the fixed half (code).
+// Low pass only: the rows whose middle bond (q-1, q) is anti-aligned are
+// u >= msplit (hi even) or u < msplit (hi odd), msplit = C(q-1, k_lo), and their
+// flip targets are the consecutive rows mbase + u of the block hi ^ 1.
+struct SplitTile {
+  int32_t row0;
+  int32_t nrows;
+  uint32_t code;
+  int32_t aux;
+  double E;
+  int32_t mbase;
+  int32_t msplit;
+};
+
+// Tables of the split apply, built once per sector (sizes 2^q and 2^(L-q)).
+struct SplitTables {
+  bool ok = false;
+  int q = 0, Lh = 0;
+  int maxrows[2] = {0, 0};       // largest tile of the low [0] / high [1] pass
+  int maxmid = 0;                // most middle-bond rows of one low-pass tile
+  int ntiles[2] = {0, 0};
+  int xcd_first[2][9] = {};      // per pass: tiles [xcd_first[x], xcd_first[x+1]) go to XCD x
+  DevBuf tiles[2];               // SplitTile lists of the two passes
+  DevBuf lo_info, hi_info;       // uint32: configurations sorted by (up spins, value), packed
+  DevBuf lo_E, hi_E;             // double, parallel to lo_info / hi_info
+  DevBuf hoff;                   // uint32, parallel to hi_info: first row of that hi's block
+  DevBuf Elo_v, Ehi_v;           // double by value (for the diagonal kernel)
+};
+
 // Per-sector Hamiltonian data (the opaque mbl_ham).
 struct Ham {
   int L = 0, nup = 0;
@@ -97,8 +138,8 @@ struct Ham {
   DevBuf pascal;   // uint32 C[33][33]
   DevBuf states;   // uint32 [n]
   DevBuf diag;     // double [n]  <s|H|s>
-  DevBuf diag32;   // float  [n]  (same values rounded)
   std::vector<uint32_t> pascal_host;
+  SplitTables split;
 };
 
 // Host Pascal table C[i][t] (row-major, 33 x 33), 0 where t > i.
@@ -113,10 +154,49 @@ struct PcgCoef {
   int pad;
 };
 
+// Block CG vectors of one column chunk (w columns) for the split CG steps.
+template <class T>
+struct SplitCg {
+  T* x;
+  int64_t ldx;
+  T* r;
+  int64_t ldr;
+  T* p;
+  int64_t ldp;
+  T* t;
+  int64_t ldt;
+  const PcgCoef* coef;
+  double* part;
+  int w;
+};
+// The chunk can run the split CG steps (usable path, 16-byte aligned vectors).
+template <class T>
+bool split_cg_ready(const Ham& H, const SplitCg<T>& c);
+// Enqueues one fused CG apply through the two passes.
+//   op 0: p = M^-1 r + beta p (live columns), t = (H - sigma) p, |t|^2 partials
+//   op 1: r -= alpha (H - sigma) t, x += alpha p, r.M^-1 r partials (x in the
+//         first pass)
+// Partials go to c.part as [column][workgroup]; returns the workgroup count
+// per column for the fold kernel.
+template <class T>
+int split_cg_apply(const Ham& H, double sigma, int op, const SplitCg<T>& c, hipStream_t s);
+
 // Apply launcher: Y = (H - sigma) X over columns [0, w).
 template <class T>
 void launch_apply(const Ham& H, double sigma, const T* X, int64_t ldx, T* Y, int64_t ldy, int w,
                   hipStream_t s);
+
+// Split (two-pass) apply, an alternative to the one-pass kernel selected with
+// MBL_APPLY_SPLIT=1.  split_usable: switched on, the sector has split tables and
+// a launch plan exists for rows of row_bytes (whole 16-byte vectors).
+// split_apply enqueues Y = (H - sigma) X, or returns false, enqueuing nothing,
+// when the path is off or the pointers / strides are not 16-byte aligned.
+bool split_usable(const Ham& H, int row_bytes);
+template <class T>
+bool split_apply(const Ham& H, double sigma, const T* X, int64_t ldx, T* Y, int64_t ldy, int w,
+                 hipStream_t s);
+// Builds H.split (host tables, uploaded with stream s).
+void build_split_tables(Ham& H, hipStream_t s);
 
 // Optional HIP-event timing of the two fused CG apply kernels.
 struct PcgTiming {
@@ -126,6 +206,7 @@ struct PcgTiming {
   int64_t launches[2] = {0, 0};
   double ms[2] = {0, 0};
   double bytes[2] = {0, 0};  // algorithmic bytes of the timed launches
+  bool split = false;        // the timed steps ran the two-pass kernels
   void init();
   ~PcgTiming();
 };

@@ -65,34 +65,25 @@ __global__ __launch_bounds__(256) void k_rank(const uint64_t* __restrict__ q, in
   out[i] = r;
 }
 
+// <s|H|s> = E_lo(lo) + E_hi(hi) + E_mid for s = (hi << q) | lo: each half's
+// energy (its inner ZZ bonds, +-J Delta / 4 for aligned / anti-aligned, and
+// its fields h_i (b_i - 1/2)) from a table, plus the ZZ term of the bond
+// (q-1, q).  The split apply kernels evaluate the same sum in the same order.
 struct DiagArgs {
-  int L;
-  double J, Delta, hsum;
-  double h[kMaxL];
+  int q;
+  double zz4;
+  const double* Elo;
+  const double* Ehi;
 };
 
-// <s|H|s>: the ZZ term gives +1/4 per aligned bond and -1/4 per anti-aligned
-// one, J*Delta*(L-1-2*nd)/4 with nd the number of anti-aligned bonds; the
-// field term is sum_i h_i (b_i - 1/2).
-__device__ inline double diag_energy(uint32_t s, const DiagArgs& a, int* nd_out) {
-  const uint32_t bondmask = (a.L >= 2) ? ((1u << (a.L - 1)) - 1u) : 0u;
-  const int nd = __popc((s ^ (s >> 1)) & bondmask);
-  double f = 0.0;
-  for (int i = 0; i < a.L; ++i)
-    if ((s >> i) & 1u) f += a.h[i];
-  *nd_out = nd;
-  return a.J * a.Delta * 0.25 * (double)(a.L - 1 - 2 * nd) + (f - 0.5 * a.hsum);
-}
-
 __global__ __launch_bounds__(256) void k_diag(const uint32_t* __restrict__ states, int64_t n,
-                                              DiagArgs a, double* __restrict__ d64,
-                                              float* __restrict__ d32) {
+                                              DiagArgs a, double* __restrict__ d64) {
   const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (r >= n) return;
-  int nd;
-  const double e = diag_energy(states[r], a, &nd);
-  d64[r] = e;
-  if (d32) d32[r] = (float)e;
+  const uint32_t s = states[r];
+  const uint32_t lo = s & ((1u << a.q) - 1u), hi = s >> a.q;
+  const bool anti = (((lo >> (a.q - 1)) ^ hi) & 1u) != 0;
+  d64[r] = (a.Elo[lo] + a.Ehi[hi]) + (anti ? -a.zz4 : a.zz4);
 }
 
 // Jacobi diagonal of (H - sigma)^2: row r of H - sigma has (E - sigma) on the
@@ -121,18 +112,18 @@ void build_tables(Ham& H, hipStream_t s) {
                          hipMemcpyHostToDevice, s));
   H.states.reset_persistent((size_t)H.n * sizeof(uint32_t));
   H.diag.reset_persistent((size_t)H.n * sizeof(double));
-  H.diag32.reset_persistent((size_t)H.n * sizeof(float));
   hipLaunchKernelGGL(k_unrank, dim3(grid1(H.n)), dim3(256), 0, s, H.states.as<uint32_t>(), H.n,
                      H.L, H.nup, H.pascal.as<uint32_t>());
   MBL_CHECK_LAUNCH();
+  build_split_tables(H, s);
+  if (!H.split.ok) fail(MBL_EINTERNAL, "sector tables: chain too short to split");
   DiagArgs a{};
-  a.L = H.L;
-  a.J = H.J;
-  a.Delta = H.Delta;
-  a.hsum = H.hsum;
-  for (int i = 0; i < H.L; ++i) a.h[i] = H.h[i];
+  a.q = H.split.q;
+  a.zz4 = 0.25 * H.J * H.Delta;
+  a.Elo = H.split.Elo_v.as<double>();
+  a.Ehi = H.split.Ehi_v.as<double>();
   hipLaunchKernelGGL(k_diag, dim3(grid1(H.n)), dim3(256), 0, s, H.states.as<uint32_t>(), H.n, a,
-                     H.diag.as<double>(), H.diag32.as<float>());
+                     H.diag.as<double>());
   MBL_CHECK_LAUNCH();
 }
 
