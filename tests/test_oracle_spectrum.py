@@ -141,3 +141,42 @@ def test_clusters_group_near_degenerate_levels():
     ev = np.array([0.0, 1e-12, 1.0, 2.0, 2.0 + 5e-10, 2.0 + 1e-9, 3.0])
     assert linalg.clusters(ev, 1e-9) == [[0, 1], [2], [3, 4, 5], [6]]
     assert linalg.clusters(ev, 1e-13) == [[0], [1], [2], [3], [4], [5], [6]]
+
+
+def test_residual_norms_known_answers():
+    """The checker behind every 'residual <= tol' claim, against residuals
+    fixed by construction: an exact eigenpair with lambda shifted by delta
+    scores |delta|; a rescaled column scores as its unit vector; a vector
+    tilted by angle t off an eigenvector u towards another w scores
+    sin t |lambda_w - lambda_u| at lambda_u and sin t cos t |lambda_w - lambda_u|
+    at its Rayleigh quotient; nev < n and nev = n shapes; a random vector is
+    far from any eigenvector."""
+    L, k = 10, 5
+    h = np.random.default_rng(5).uniform(-3, 3, L)
+    _, H = hamiltonian.sector_matrix(L, k, 1.0, 1.0, h)
+    w, V = np.linalg.eigh(H.toarray())
+    n = len(w)
+    # exact pairs: residual at rounding level, for nev = n and nev = 3
+    assert linalg.residual_norms(H, w, V).max() < 1e-12
+    assert linalg.residual_norms(H, w[[0, 7, n - 1]], V[:, [0, 7, n - 1]]).shape == (3,)
+    # shifted eigenvalues score exactly the shift
+    deltas = np.array([1e-3, -2.5e-6, 0.75])
+    cols = [3, 40, 200]
+    r = linalg.residual_norms(H, w[cols] + deltas, V[:, cols])
+    np.testing.assert_allclose(r, np.abs(deltas), rtol=1e-9)
+    # non-unit columns are normalised first
+    r2 = linalg.residual_norms(H, w[cols] + deltas, V[:, cols] * np.array([3.0, 1e-4, -7.0]))
+    np.testing.assert_allclose(r2, r, rtol=1e-9)
+    # a vector tilted between two eigenvectors
+    u, v2 = 10, 11
+    t = 0.2
+    x = np.cos(t) * V[:, u] + np.sin(t) * V[:, v2]
+    gap = abs(w[v2] - w[u])
+    want = np.sin(t) * gap  # at lambda_u only the w-part leaves a residual
+    np.testing.assert_allclose(linalg.residual_norms(H, [w[u]], x[:, None]), [want], rtol=1e-9)
+    rq = np.cos(t) ** 2 * w[u] + np.sin(t) ** 2 * w[v2]
+    np.testing.assert_allclose(linalg.residual_norms(H, [rq], x[:, None]),
+                               [np.sin(t) * np.cos(t) * gap], rtol=1e-9)
+    # a random vector is not an eigenvector
+    rnd = np.random.default_rng(0).standard_normal(n)
+    assert linalg.residual_norms(H, [0.0], rnd[:, None])[0] > 0.1
