@@ -52,6 +52,8 @@ typedef enum {
   MBL_ENOCONV = -4,     /* solver hit its iteration limit; best pairs returned */
   MBL_EBREAKDOWN = -5,  /* basis collapsed (e.g. starting block rank-deficient) */
   MBL_ETIMEOUT = -6,    /* mbl_server_wait: request not finished in time      */
+  MBL_ECANCELLED = -7,  /* solve stopped by its cancel flag or time limit (or
+                           a server request cancelled); best pairs returned  */
   MBL_EINTERNAL = -8    /* unexpected internal failure                        */
 } mbl_status;
 
@@ -187,6 +189,23 @@ typedef struct {
                             active), so the inner CG runs on fewer columns.
                             Results satisfy the same tolerance; iterates
                             differ from lock = 0.  Default 0.               */
+  double max_seconds;    /* > 0: wall-clock limit of the call.  Checked
+                            between outer iterations and every 32 CG steps;
+                            when it passes, the solve finishes the CG chunk
+                            in flight, extracts the current best pairs with
+                            fresh FP64 residuals and returns MBL_ECANCELLED
+                            (MBL_OK if they already meet tol).  0 = none.   */
+  const volatile int* cancel;  /* host flag, may be NULL: a nonzero value
+                            stops the solve the same way (set it from
+                            another thread).                                 */
+  double guard_cg;       /* fraction (0, 1] of the pcg_iters CG steps given to
+                            the guard columns of the block (those beyond the
+                            nev smallest fold Ritz values); the nev leading
+                            columns always run all pcg_iters steps.  0 = by
+                            size: 0.1 for sectors of n >= 500000 (where the
+                            CG dominates and this is measured faster: 24%
+                            at L = 22, nev 64, block 128), else 1.  Applies
+                            without soft locking.                            */
 } mbl_solve_opts;
 
 typedef struct {
@@ -209,6 +228,11 @@ typedef struct {
   double cg_apply1_bytes[2], cg_apply2_bytes[2];
   int64_t pcg_columns;   /* CG steps times block columns, summed over inner
                             solves (fewer than pcg_steps * block with lock) */
+  /* opts.timing: device seconds (HIP events) of the applies outside the CG
+     (residual blocks, new directions, fresh residuals), the Gram products and
+     the small dense kernels (eigensolver, Cholesky, small products)        */
+  double t_apply, t_gram, t_small;
+  int cg_split;          /* the timed CG steps ran the two-pass kernels      */
 } mbl_solve_info;
 
 mbl_status mbl_solve_opts_default(mbl_solve_opts* opts);
@@ -299,14 +323,16 @@ mbl_status mbl_footprint_bytes(int L, double Sz, int block, int precision, size_
 mbl_status mbl_batch_solve(int count, const mbl_problem* problems, mbl_result* results,
                            int concurrency);
 
-/* Serving loop with continuous batching: submit() queues a request and returns
- * at once; `concurrency` worker threads take requests in arrival order as soon
- * as a worker is free and the sum of admitted footprints stays within
- * hbm_budget (bytes; 0 = 90% of the device's free memory), so requests that
- * arrive while others run are started beside them.  A request whose footprint
- * exceeds the whole budget is refused at submit (MBL_ENOMEM).  wait() blocks
- * for a ticket (timeout_s < 0: forever) and fills `out` (its buffers must stay
- * valid until wait returns).  Results are kept until waited for.  Thread-safe. */
+/* Serving loop with continuous batching on HIP device `device`: submit()
+ * queues a request and returns at once; `max_slots` worker threads take
+ * requests in arrival order as soon as a slot is free and the sum of admitted
+ * footprints stays within hbm_budget (bytes; 0 = 90% of the device's free
+ * memory at creation), so requests that arrive while others run are started
+ * beside them.  A request whose footprint exceeds the whole budget is refused
+ * at submit (MBL_ENOMEM).  wait() blocks for a ticket (timeout_s < 0: forever)
+ * and fills `out` (its buffers must stay valid until wait returns).  Results
+ * are kept until waited for.  Thread-safe.  The statistics call is named
+ * mbl_server_stats_get because mbl_server_stats names its struct. */
 typedef struct mbl_server_s* mbl_server;
 typedef struct {
   int64_t submitted, admitted, completed, rejected, in_flight;
@@ -315,11 +341,16 @@ typedef struct {
   size_t budget_bytes, peak_bytes;
 } mbl_server_stats;
 
-mbl_status mbl_server_create(int concurrency, size_t hbm_budget, mbl_server* out);
+mbl_status mbl_server_create(int device, size_t hbm_budget, int max_slots, mbl_server* out);
 mbl_status mbl_server_submit(mbl_server srv, const mbl_problem* request, uint64_t* ticket);
 /* Returns MBL_OK when the request finished (its own status is out->status),
  * MBL_ETIMEOUT if it is still running after timeout_s. */
 mbl_status mbl_server_wait(mbl_server srv, uint64_t ticket, double timeout_s, mbl_result* out);
+/* Cancels a request that has not finished: a queued one is dropped, a running
+ * one stops within one chunk of CG steps.  Its result (still to be waited for)
+ * has status MBL_ECANCELLED (a running solve returns its best pairs so far).
+ * MBL_EINVAL for an unknown or already finished ticket. */
+mbl_status mbl_server_cancel(mbl_server srv, uint64_t ticket);
 mbl_status mbl_server_stats_get(mbl_server srv, mbl_server_stats* st);
 /* Waits for every submitted request, then stops the workers. */
 mbl_status mbl_server_destroy(mbl_server srv);

@@ -12,17 +12,19 @@ LIB_PATH = os.environ.get("MBL_LIBRARY") or os.path.join(HERE, "libmbl.so")
 
 MBL_OK, MBL_EINVAL, MBL_ENOMEM, MBL_EDEVICE, MBL_ENOCONV, MBL_EBREAKDOWN, MBL_ETIMEOUT = (
     0, -1, -2, -3, -4, -5, -6)
-MBL_EINTERNAL = -8
+MBL_ECANCELLED, MBL_EINTERNAL = -7, -8
 MBL_F64, MBL_F32, MBL_MIXED, MBL_PCG32 = 0, 1, 2, 3
 
 STATUS_NAMES = {0: "MBL_OK", -1: "MBL_EINVAL", -2: "MBL_ENOMEM", -3: "MBL_EDEVICE",
-                -4: "MBL_ENOCONV", -5: "MBL_EBREAKDOWN", -6: "MBL_ETIMEOUT", -8: "MBL_EINTERNAL"}
+                -4: "MBL_ENOCONV", -5: "MBL_EBREAKDOWN", -6: "MBL_ETIMEOUT", -7: "MBL_ECANCELLED",
+                -8: "MBL_EINTERNAL"}
 
 
 class SolveOpts(C.Structure):
     _fields_ = [("max_iter", C.c_int), ("pcg_iters", C.c_int), ("precision", C.c_int),
                 ("verbose", C.c_int), ("timing", C.c_int), ("seed", C.c_uint64),
-                ("lock", C.c_int)]
+                ("lock", C.c_int), ("max_seconds", C.c_double), ("cancel", C.POINTER(C.c_int)),
+                ("guard_cg", C.c_double)]
 
 
 class SolveInfo(C.Structure):
@@ -32,7 +34,8 @@ class SolveInfo(C.Structure):
                 ("cg_apply1_launches", C.c_int64 * 2), ("cg_apply2_launches", C.c_int64 * 2),
                 ("cg_apply1_ms", C.c_double * 2), ("cg_apply2_ms", C.c_double * 2),
                 ("cg_apply1_bytes", C.c_double * 2), ("cg_apply2_bytes", C.c_double * 2),
-                ("pcg_columns", C.c_int64)]
+                ("pcg_columns", C.c_int64), ("t_apply", C.c_double), ("t_gram", C.c_double),
+                ("t_small", C.c_double), ("cg_split", C.c_int)]
 
 
 class Problem(C.Structure):
@@ -59,6 +62,10 @@ class ServerStats(C.Structure):
 
 
 vp, i64, dbl, cint = C.c_void_p, C.c_int64, C.c_double, C.c_int
+
+# mbl_alloc_fn / mbl_free_fn
+AllocFn = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FreeFn = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
 dptr = C.POINTER(C.c_double)
 u64p = C.POINTER(C.c_uint64)
 i64p = C.POINTER(C.c_int64)
@@ -66,7 +73,7 @@ i64p = C.POINTER(C.c_int64)
 PROTOTYPES = {
     "mbl_last_error": (C.c_char_p, []),
     "mbl_version": (cint, []),
-    "mbl_set_allocator": (cint, [vp, vp, vp]),
+    "mbl_set_allocator": (cint, [AllocFn, FreeFn, vp]),
     "mbl_hamiltonian_create": (cint, [cint, dbl, dbl, dbl, dptr, vp, C.POINTER(vp)]),
     "mbl_hamiltonian_destroy": (cint, [vp]),
     "mbl_hamiltonian_dim": (cint, [vp, i64p]),
@@ -89,7 +96,8 @@ PROTOTYPES = {
     "mbl_slices_solve": (cint, [vp, cint, dptr, cint, cint, dbl, C.POINTER(SolveOpts), dptr, dptr,
                                 cint]),
     "mbl_batch_solve": (cint, [cint, C.POINTER(Problem), C.POINTER(Result), cint]),
-    "mbl_server_create": (cint, [cint, C.c_size_t, C.POINTER(vp)]),
+    "mbl_server_create": (cint, [cint, C.c_size_t, cint, C.POINTER(vp)]),
+    "mbl_server_cancel": (cint, [vp, C.c_uint64]),
     "mbl_server_submit": (cint, [vp, C.POINTER(Problem), C.POINTER(C.c_uint64)]),
     "mbl_server_wait": (cint, [vp, C.c_uint64, dbl, C.POINTER(Result)]),
     "mbl_server_stats_get": (cint, [vp, C.POINTER(ServerStats)]),

@@ -5,7 +5,10 @@ torch tensors into device pointers and streams and checks status codes.
 Blocks are row-major (n, b) tensors on a HIP device; FP64 or FP32.
 """
 
+import atexit
 import ctypes as C
+import os
+import weakref
 
 import numpy as np
 import torch
@@ -14,6 +17,78 @@ from . import _lib
 from ._lib import MBL_F32, MBL_F64, MBL_MIXED, MBL_PCG32, MblError  # noqa: F401
 
 PRECISIONS = {"f64": MBL_F64, "mixed": MBL_MIXED, "pcg32": MBL_PCG32}
+
+
+# -- device memory -------------------------------------------------------------
+# The library's device work space is taken from torch's caching allocator
+# through mbl_set_allocator, so one pool owns all device memory: what a solve
+# frees goes back to torch and is reused by tensors and by later solves.  The
+# callbacks receive the library's stream; torch keeps the block stream-ordered
+# on it.  MBL_TORCH_ALLOCATOR=0 leaves the library on its own stream-ordered
+# pool.
+def _torch_alloc(nbytes, stream, ctx):
+    try:
+        torch.cuda._lazy_init()
+        return torch._C._cuda_cudaCachingAllocator_raw_alloc(int(nbytes), int(stream or 0))
+    except Exception:
+        return None  # the library reports MBL_ENOMEM
+
+
+def _torch_free(ptr, stream, ctx):
+    torch._C._cuda_cudaCachingAllocator_raw_delete(int(ptr))
+
+
+_allocator = None  # (alloc, free) ctypes callbacks in use
+# Every pair ever installed stays alive: buffers are freed by the callback that
+# allocated them, which may be long after another pair was installed.
+_installed = []
+_handles = weakref.WeakSet()  # open Hamiltonians and servers
+
+
+def use_allocator(alloc=None, free=None):
+    """Install device allocation callbacks: alloc(nbytes, stream) -> int
+    pointer (0 on failure) and free(ptr, stream); (None, None) restores the
+    library's own pool.  Buffers are always released by the allocator that
+    made them."""
+    global _allocator
+    lib = _lib.load()
+    if alloc is None:
+        _lib.check(lib.mbl_set_allocator(_lib.AllocFn(), _lib.FreeFn(), None))
+        _allocator = None
+        return
+    cb = (_lib.AllocFn(lambda n, s, c: alloc(n, s)), _lib.FreeFn(lambda p, s, c: free(p, s)))
+    _installed.append(cb)
+    _lib.check(lib.mbl_set_allocator(cb[0], cb[1], None))
+    _allocator = cb
+
+
+def use_torch_allocator():
+    """Route the library's device memory through torch's caching allocator."""
+    use_allocator(lambda n, s: _torch_alloc(n, s, None), lambda p, s: _torch_free(p, s, None))
+
+
+def _install_default_allocator():
+    if os.environ.get("MBL_TORCH_ALLOCATOR", "1") == "0":
+        return
+    try:
+        use_torch_allocator()
+    except ImportError:
+        pass  # library not built: the first solver call raises
+
+
+@atexit.register
+def _release_at_exit():
+    # close what is still open while the callbacks can still run
+    for obj in list(_handles):
+        try:
+            obj.close()
+        except Exception:
+            pass
+    if _allocator is not None:
+        try:
+            use_allocator(None)
+        except Exception:
+            pass
 
 
 def _stream(stream=None):
@@ -55,6 +130,7 @@ class Hamiltonian:
         n = C.c_int64()
         _lib.check(lib.mbl_hamiltonian_dim(self._h, C.byref(n)))
         self.n = n.value
+        _handles.add(self)
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -162,11 +238,15 @@ class Hamiltonian:
 
     def solve(self, sigma, nev, block, tol=1e-10, precision="f64", max_iter=400, pcg_iters=0,
               seed=0x5EED, verbose=False, want_vectors=True, device="cuda", stream=None,
-              raise_on_noconv=True, timing=False, lock=False):
+              raise_on_noconv=True, timing=False, lock=False, max_seconds=0.0, cancel=None,
+              guard_cg=0.0):
         """nev eigenpairs nearest sigma by LOBPCG on the spectral fold.
 
         lock=True turns on soft locking of converged wanted pairs (the inner
-        CG then runs on fewer columns; see mbl_solve_opts.lock).
+        CG then runs on fewer columns; see mbl_solve_opts.lock).  max_seconds
+        > 0 limits the wall time and `cancel` (a ctypes.c_int another thread
+        may set nonzero) stops the solve; both return the best pairs so far
+        with status MBL_ECANCELLED (raised unless raise_on_noconv is False).
 
         Returns (evals [nev] numpy, evecs (n, nev) float64 tensor or None,
         resid [nev] numpy, info dict).
@@ -177,10 +257,14 @@ class Hamiltonian:
         opts.max_iter = int(max_iter)
         opts.pcg_iters = int(pcg_iters)
         opts.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
-        opts.verbose = int(bool(verbose))
+        opts.verbose = int(verbose)
         opts.timing = int(bool(timing))
         opts.seed = int(seed)
         opts.lock = int(bool(lock))
+        opts.max_seconds = float(max_seconds)
+        opts.guard_cg = float(guard_cg)
+        if cancel is not None:
+            opts.cancel = C.pointer(cancel)
         ev = np.zeros(nev)
         rs = np.zeros(nev)
         info = _lib.SolveInfo()
@@ -189,7 +273,7 @@ class Hamiltonian:
             self._h, float(sigma), int(nev), int(block), float(tol), C.byref(opts),
             ev.ctypes.data_as(_lib.dptr), C.c_void_p(V.data_ptr()) if V is not None else None,
             nev, rs.ctypes.data_as(_lib.dptr), C.byref(info), _stream(stream))
-        _lib.check(st, allow=() if raise_on_noconv else (_lib.MBL_ENOCONV,))
+        _lib.check(st, allow=() if raise_on_noconv else (_lib.MBL_ENOCONV, _lib.MBL_ECANCELLED))
         d = {}
         for f, _ in _lib.SolveInfo._fields_:
             v = getattr(info, f)
@@ -321,12 +405,14 @@ def batch_solve(problems, concurrency=4, vectors=False, device="cuda"):
 class Server:
     """Serving loop with continuous batching and HBM-footprint admission."""
 
-    def __init__(self, concurrency=4, hbm_budget=0):
+    def __init__(self, max_slots=4, hbm_budget=0, device=None):
         self._lib = _lib.load()
+        dev = torch.cuda.current_device() if device is None else int(device)
         h = C.c_void_p()
-        _lib.check(self._lib.mbl_server_create(int(concurrency), int(hbm_budget), C.byref(h)))
+        _lib.check(self._lib.mbl_server_create(dev, int(hbm_budget), int(max_slots), C.byref(h)))
         self._s = h
         self._keep = {}
+        _handles.add(self)
 
     def submit(self, problem):
         pr = _problem(dict(problem))
@@ -352,6 +438,11 @@ class Server:
         del self._keep[ticket]
         return _result_dict(r, ev, rs)
 
+    def cancel(self, ticket):
+        """Cancel a request that has not finished (its result, still to be
+        waited for, then has status MBL_ECANCELLED)."""
+        _lib.check(self._lib.mbl_server_cancel(self._s, int(ticket)))
+
     def stats(self):
         st = _lib.ServerStats()
         _lib.check(self._lib.mbl_server_stats_get(self._s, C.byref(st)))
@@ -373,3 +464,6 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+_install_default_allocator()

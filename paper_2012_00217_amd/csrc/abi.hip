@@ -68,13 +68,19 @@ void prepare_pool() {
 }
 }  // namespace
 
-void* dev_alloc(size_t bytes, hipStream_t s, bool ordered) {
+void* dev_alloc(size_t bytes, hipStream_t s, bool ordered, AllocOwner* owner) {
   void* p = nullptr;
+  owner->s = s;
+  owner->ordered = ordered;
   if (g_alloc) {
     p = g_alloc(bytes, s, g_ctx);
     if (!p) fail(MBL_ENOMEM, "allocator callback returned NULL for " + std::to_string(bytes) + " bytes");
+    owner->free_fn = g_free;
+    owner->ctx = g_ctx;
     return p;
   }
+  owner->free_fn = nullptr;
+  owner->ctx = nullptr;
   if (ordered) {
     prepare_pool();
     MBL_HIP(hipMallocAsync(&p, bytes, s));
@@ -84,19 +90,20 @@ void* dev_alloc(size_t bytes, hipStream_t s, bool ordered) {
   return p;
 }
 
-void dev_free(void* p, hipStream_t s, bool ordered) {
+void dev_free(void* p, const AllocOwner& o) {
   if (!p) return;
-  if (g_free) {
-    g_free(p, s, g_ctx);
+  if (o.free_fn) {
+    o.free_fn(p, o.s, o.ctx);
     return;
   }
-  if (ordered)
-    (void)hipFreeAsync(p, s);
+  if (o.ordered)
+    (void)hipFreeAsync(p, o.s);
   else
     (void)hipFree(p);
 }
 
-Ham* create_ham(int L, double Sz, double J, double Delta, const double* h_host, hipStream_t stream) {
+Ham* create_ham(int L, double Sz, double J, double Delta, const double* h_host, hipStream_t stream,
+                hipStream_t home) {
   require(L >= 2 && L <= kMaxL, "L must be in [2, 32]");
   require(std::isfinite(Sz) && std::isfinite(J) && std::isfinite(Delta), "Sz, J, Delta must be finite");
   const double two = 2.0 * Sz;
@@ -107,6 +114,7 @@ Ham* create_ham(int L, double Sz, double J, double Delta, const double* h_host, 
   require(h_host != nullptr, "h is NULL");
   for (int i = 0; i < L; ++i) require(std::isfinite(h_host[i]), "h must be finite");
   auto* H = new Ham();
+  H->home = home;
   try {
     H->L = L;
     H->nup = (int)((tsz + L) / 2);
@@ -171,6 +179,8 @@ mbl_status mbl_hamiltonian_create(int L, double Sz, double J, double Delta, cons
 
 mbl_status mbl_hamiltonian_destroy(mbl_ham h) {
   return guard([&] {
+    // kernels of any stream may still read the tables
+    if (h) MBL_HIP(hipDeviceSynchronize());
     delete reinterpret_cast<Ham*>(h);
     return MBL_OK;
   });
@@ -396,6 +406,9 @@ mbl_status mbl_lobpcg_solve(mbl_ham h, double sigma, int nev, int block, double 
     require(o.precision == MBL_F64 || o.precision == MBL_MIXED || o.precision == MBL_PCG32,
             "precision must be MBL_F64, MBL_MIXED or MBL_PCG32");
     require(o.max_iter >= 0 && o.pcg_iters >= 0, "negative iteration count");
+    require(std::isfinite(o.max_seconds) && o.max_seconds >= 0, "max_seconds must be >= 0");
+    require(std::isfinite(o.guard_cg) && o.guard_cg >= 0 && o.guard_cg <= 1,
+            "guard_cg must be in [0, 1]");
     if (info) std::memset(info, 0, sizeof(*info));
     return solve_interior(H, sigma, nev, block, tol, o, evals_host, evecs_dev, ldv, resid_host, info, s);
   });
@@ -466,12 +479,15 @@ mbl_status mbl_batch_solve(int count, const mbl_problem* problems, mbl_result* r
 
 struct mbl_server_s {};
 
-mbl_status mbl_server_create(int concurrency, size_t hbm_budget, mbl_server* out) {
+mbl_status mbl_server_create(int device, size_t hbm_budget, int max_slots, mbl_server* out) {
   return guard([&] {
     require(out != nullptr, "out is NULL");
-    require(concurrency >= 1 && concurrency <= 64, "concurrency must be in [1, 64]");
+    require(max_slots >= 1 && max_slots <= 64, "max_slots must be in [1, 64]");
+    int ndev = 0;
+    MBL_HIP(hipGetDeviceCount(&ndev));
+    require(device >= 0 && device < ndev, "no such device");
     Server* srv = nullptr;
-    server_create(concurrency, hbm_budget, &srv);
+    server_create(device, max_slots, hbm_budget, &srv);
     *out = reinterpret_cast<mbl_server>(srv);
     return MBL_OK;
   });
@@ -488,6 +504,13 @@ mbl_status mbl_server_wait(mbl_server srv, uint64_t ticket, double timeout_s, mb
   return guard([&] {
     require(srv && out, "NULL argument");
     return server_wait(reinterpret_cast<Server*>(srv), ticket, timeout_s, out);
+  });
+}
+
+mbl_status mbl_server_cancel(mbl_server srv, uint64_t ticket) {
+  return guard([&] {
+    require(srv != nullptr, "NULL server");
+    return server_cancel(reinterpret_cast<Server*>(srv), ticket);
   });
 }
 

@@ -643,6 +643,7 @@ template <class T>
 void launch_apply(const Ham& H, double sigma, const T* X, int64_t ldx, T* Y, int64_t ldy, int w,
                   hipStream_t s) {
   if (H.n == 0 || w == 0) return;
+  PhaseTick tick(PhaseClock::APPLY, s);
   if (split_apply<T>(H, sigma, X, ldx, Y, ldy, w, s)) return;
   const bool aligned = al16(X, ldx, sizeof(T)) && al16(Y, ldy, sizeof(T));
   ApplyArgs<T> a = base_args<T>(H, sigma);
@@ -696,14 +697,21 @@ int pcg_chunk_width(int64_t n, int b) {
 // least 8 steps remain, else launch by launch.  The legacy default stream
 // cannot be captured, and a capture on a caller's blocking stream would forbid
 // legacy-stream work in every other thread of the process meanwhile.
+// With a stop check the replays are issued in chunks of kStopChunk, one chunk
+// queued ahead of the one running, and no further chunk is issued once the
+// check triggers.  Returns the number of steps run.
+constexpr int kStopChunk = 32;
+
 template <class F>
-void replay_steps(F&& step, int it, int m, hipStream_t& s) {
+int replay_steps(F&& step, int it, int m, hipStream_t& s, const StopCheck* stop) {
   if (env_int("MBL_PCG_GRAPH", 1) != 0 && m - it >= 8) {
     hipStream_t own = nullptr;
-    hipEvent_t fork = nullptr, join = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr, mark[2] = {nullptr, nullptr};
     MBL_HIP(hipStreamCreateWithFlags(&own, hipStreamNonBlocking));
     hipError_t err = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
     if (err == hipSuccess) err = hipEventCreateWithFlags(&join, hipEventDisableTiming);
+    for (int k = 0; k < 2 && err == hipSuccess; ++k)
+      err = hipEventCreateWithFlags(&mark[k], hipEventDisableTiming);
     if (err == hipSuccess) err = hipEventRecord(fork, s);
     if (err == hipSuccess) err = hipStreamWaitEvent(own, fork, 0);
     hipGraph_t graph = nullptr;
@@ -723,13 +731,25 @@ void replay_steps(F&& step, int it, int m, hipStream_t& s) {
         (void)hipStreamDestroy(own);
         (void)hipEventDestroy(fork);
         (void)hipEventDestroy(join);
+        for (hipEvent_t e : mark)
+          if (e) (void)hipEventDestroy(e);
         throw;
       }
       s = keep;
       err = hipStreamEndCapture(own, &graph);
     }
     if (err == hipSuccess) err = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    for (; err == hipSuccess && it < m; ++it) err = hipGraphLaunch(exec, own);
+    int chunk = 0;
+    while (err == hipSuccess && it < m) {
+      const int end = stop ? std::min(m, it + kStopChunk) : m;
+      for (; err == hipSuccess && it < end; ++it) err = hipGraphLaunch(exec, own);
+      if (!stop || err != hipSuccess || it >= m) continue;
+      // wait for the chunk before this one, then decide whether to go on
+      err = hipEventRecord(mark[chunk & 1], own);
+      if (err == hipSuccess && chunk > 0) err = hipEventSynchronize(mark[(chunk - 1) & 1]);
+      ++chunk;
+      if (err == hipSuccess && stop->triggered()) break;
+    }
     if (err == hipSuccess) err = hipEventRecord(join, own);
     if (err == hipSuccess) err = hipStreamWaitEvent(s, join, 0);
     // the graph and its stream are torn down only after the replays finished
@@ -739,10 +759,17 @@ void replay_steps(F&& step, int it, int m, hipStream_t& s) {
     (void)hipStreamDestroy(own);
     if (fork) (void)hipEventDestroy(fork);
     if (join) (void)hipEventDestroy(join);
+    for (hipEvent_t e : mark)
+      if (e) (void)hipEventDestroy(e);
     MBL_HIP(err);
     MBL_HIP(se);
+    return it;
   }
-  for (; it < m; ++it) step();
+  for (; it < m; ++it) {
+    if (stop && it % kStopChunk == 0 && stop->triggered()) break;
+    step();
+  }
+  return it;
 }
 
 // Block PCG of one column chunk through the split (two-pass) kernels:
@@ -754,7 +781,7 @@ void replay_steps(F&& step, int it, int m, hipStream_t& s) {
 template <class T>
 void run_pcg_split(const Ham& H, double sigma, const T* jac, const T* Rc, int64_t ldr,
                    const SplitCg<T>& sg, int m, bool aligned, const Sched& sc, hipStream_t s,
-                   PcgTiming* tm) {
+                   PcgTiming* tm, const StopCheck* stop) {
   const int64_t n = H.n;
   const int w = sg.w;
   for (const Chunk& ch : plan_chunks<T>(w, aligned, sc)) {
@@ -801,7 +828,7 @@ void run_pcg_split(const Ham& H, double sigma, const T* jac, const T* Rc, int64_
     const int nwp2 = split_cg_apply<T>(H, sigma, 1, sg, s);
     fin(nwp2, FB{}, s);
   };
-  replay_steps(step, it, m, s);
+  replay_steps(step, it, m, s, stop);
   if (ntimed > 0) {
     MBL_HIP(hipStreamSynchronize(s));
     for (int k = 0; k < ntimed; ++k) {
@@ -823,7 +850,8 @@ void run_pcg_split(const Ham& H, double sigma, const T* jac, const T* Rc, int64_
 
 template <class T>
 void run_pcg(const Ham& H, double sigma, const T* jac, const T* R, int64_t ldr, T* W, int64_t ldw,
-             int b, int m, hipStream_t s, PcgTiming* tm) {
+             int b, int m, hipStream_t s, PcgTiming* tm, const StopCheck* stop, int keep,
+             int m_keep) {
   const int64_t n = H.n;
   if (n == 0 || b == 0) return;
   const int wc = pcg_chunk_width<T>(n, b);
@@ -848,18 +876,17 @@ void run_pcg(const Ham& H, double sigma, const T* jac, const T* R, int64_t ldr, 
     const Sched sc = sched_for(H, w * (int)sizeof(T), (int)sizeof(T));
     SplitCg<T> sg{x, ldx, r, w, p, w, t, w, cf, part.as<double>(), w};
     if (split_cg_ready<T>(H, sg)) {
-      run_pcg_split<T>(H, sigma, jac, Rc, ldr, sg, m, aligned, sc, s, tm);
+      run_pcg_split<T>(H, sigma, jac, Rc, ldr, sg, std::max(m, m_keep), aligned, sc, s, tm, stop);
       if (wc < b)
         MBL_HIP(hipMemcpy2DAsync(W + c0, ldw * sizeof(T), x, w * sizeof(T), w * sizeof(T), n,
                                  hipMemcpyDeviceToDevice, s));
       continue;
     }
-    for (const Chunk& ch : plan_chunks<T>(w, aligned, sc)) {
-      if ((size_t)ch.w * kMaxWg * sizeof(double) > part.bytes()) fail(MBL_EINTERNAL, "pcg: part");
+    // CG steps [from, to) on the columns of chunk ch (events on the first
+    // timed steps of the solve's first pass over the chunk)
+    auto cg_steps = [&](const Chunk& ch, int from, int to, bool timed) {
       const Grid g = make_grid(n, ch.log2G, sc);
       EltArgs<T> e{};
-      e.R = Rc;
-      e.ldR = ldr;
       e.x = x;
       e.ldxv = ldx;
       e.r = r;
@@ -870,9 +897,6 @@ void run_pcg(const Ham& H, double sigma, const T* jac, const T* R, int64_t ldr, 
       e.coef = cf;
       e.part = part.as<double>();
       e.n = n;
-      dispatch_elt<T, ELT_INIT>(ch, g, e, s);
-      finalize<FIN_INIT>(ch, g, part.as<double>(), cf, s);
-
       ApplyArgs<T> a1 = base_args<T>(H, sigma);  // T = (H - sigma) p, |T|^2
       a1.X = p;
       a1.ldx = w;
@@ -891,8 +915,8 @@ void run_pcg(const Ham& H, double sigma, const T* jac, const T* R, int64_t ldr, 
       a2.jac = jac;
       a2.coef = cf;
       a2.part = part.as<double>();
-      const int ntimed = tm ? std::min(m, PcgTiming::kSample) : 0;
-      if (tm) tm->init();
+      const int ntimed = (tm && timed) ? std::min(to - from, PcgTiming::kSample) : 0;
+      if (ntimed) tm->init();
       auto step = [&]() {
         dispatch_apply<T, EPI_NORM2>(ch, g, a1, s);
         finalize<FIN_ALPHA>(ch, g, part.as<double>(), cf, s);
@@ -900,27 +924,27 @@ void run_pcg(const Ham& H, double sigma, const T* jac, const T* R, int64_t ldr, 
         finalize<FIN_BETA>(ch, g, part.as<double>(), cf, s);
         dispatch_elt<T, ELT_PUPD>(ch, g, e, s);
       };
-      int it = 0;
-      for (; it < ntimed; ++it) {
-        MBL_HIP(hipEventRecord(tm->ev[4 * it + 0], s));
+      int it = from;
+      for (int k = 0; k < ntimed; ++k, ++it) {
+        MBL_HIP(hipEventRecord(tm->ev[4 * k + 0], s));
         dispatch_apply<T, EPI_NORM2>(ch, g, a1, s);
-        MBL_HIP(hipEventRecord(tm->ev[4 * it + 1], s));
+        MBL_HIP(hipEventRecord(tm->ev[4 * k + 1], s));
         finalize<FIN_ALPHA>(ch, g, part.as<double>(), cf, s);
-        MBL_HIP(hipEventRecord(tm->ev[4 * it + 2], s));
+        MBL_HIP(hipEventRecord(tm->ev[4 * k + 2], s));
         dispatch_apply<T, EPI_PCG>(ch, g, a2, s);
-        MBL_HIP(hipEventRecord(tm->ev[4 * it + 3], s));
+        MBL_HIP(hipEventRecord(tm->ev[4 * k + 3], s));
         finalize<FIN_BETA>(ch, g, part.as<double>(), cf, s);
         dispatch_elt<T, ELT_PUPD>(ch, g, e, s);
       }
       // The remaining steps replay one captured step: every CG coefficient
       // lives on the device, so the five launches are identical each step.
-      replay_steps(step, it, m, s);
+      replay_steps(step, it, to, s, stop);
       if (ntimed > 0) {
         MBL_HIP(hipStreamSynchronize(s));
-        for (int it = 0; it < ntimed; ++it) {
+        for (int k = 0; k < ntimed; ++k) {
           float ta = 0.f, tc = 0.f;
-          MBL_HIP(hipEventElapsedTime(&ta, tm->ev[4 * it + 0], tm->ev[4 * it + 1]));
-          MBL_HIP(hipEventElapsedTime(&tc, tm->ev[4 * it + 2], tm->ev[4 * it + 3]));
+          MBL_HIP(hipEventElapsedTime(&ta, tm->ev[4 * k + 0], tm->ev[4 * k + 1]));
+          MBL_HIP(hipEventElapsedTime(&tc, tm->ev[4 * k + 2], tm->ev[4 * k + 3]));
           tm->ms[0] += ta;
           tm->ms[1] += tc;
         }
@@ -928,6 +952,42 @@ void run_pcg(const Ham& H, double sigma, const T* jac, const T* R, int64_t ldr, 
         tm->launches[1] += ntimed;
         tm->bytes[0] += (double)ntimed * (2.0 * n * ch.w * sizeof(T) + 12.0 * n);
         tm->bytes[1] += (double)ntimed * (6.0 * n * ch.w * sizeof(T) + (12.0 + sizeof(T)) * n);
+      }
+    };
+    for (const Chunk& ch : plan_chunks<T>(w, aligned, sc)) {
+      if ((size_t)ch.w * kMaxWg * sizeof(double) > part.bytes()) fail(MBL_EINTERNAL, "pcg: part");
+      {
+        const Grid g = make_grid(n, ch.log2G, sc);
+        EltArgs<T> e{};
+        e.R = Rc;
+        e.ldR = ldr;
+        e.x = x;
+        e.ldxv = ldx;
+        e.r = r;
+        e.ldr = w;
+        e.p = p;
+        e.ldp = w;
+        e.jac = jac;
+        e.coef = cf;
+        e.part = part.as<double>();
+        e.n = n;
+        dispatch_elt<T, ELT_INIT>(ch, g, e, s);
+        finalize<FIN_INIT>(ch, g, part.as<double>(), cf, s);
+      }
+      // columns [0, keep) of the whole block run m_keep steps, the others m
+      const int lo = c0 + ch.col0, hi = lo + ch.w;
+      if (hi <= keep || m_keep <= m) {
+        cg_steps(ch, 0, hi <= keep ? std::max(m, m_keep) : m, true);
+      } else {
+        cg_steps(ch, 0, m, true);
+        if (lo < keep) {
+          // the leading columns of this chunk go on (same vectors and ld)
+          for (const Chunk& sub : plan_chunks<T>(keep - lo, aligned, sc)) {
+            Chunk c2 = sub;
+            c2.col0 += ch.col0;
+            cg_steps(c2, m, m_keep, false);
+          }
+        }
       }
     }
     if (wc < b)
@@ -941,8 +1001,10 @@ template void launch_apply<double>(const Ham&, double, const double*, int64_t, d
 template void launch_apply<float>(const Ham&, double, const float*, int64_t, float*, int64_t, int,
                                   hipStream_t);
 template void run_pcg<double>(const Ham&, double, const double*, const double*, int64_t, double*,
-                              int64_t, int, int, hipStream_t, PcgTiming*);
+                              int64_t, int, int, hipStream_t, PcgTiming*, const StopCheck*, int,
+                              int);
 template void run_pcg<float>(const Ham&, double, const float*, const float*, int64_t, float*,
-                             int64_t, int, int, hipStream_t, PcgTiming*);
+                             int64_t, int, int, hipStream_t, PcgTiming*, const StopCheck*, int,
+                             int);
 
 }  // namespace mbl

@@ -705,7 +705,7 @@ void build_split_tables(Ham& H, hipStream_t s) {
     while (x <= 8) S.xcd_first[ps][x++] = (int)tl[ps].size();
   }
   auto up = [&](DevBuf& d, const void* src, size_t bytes) {
-    d.reset_persistent(std::max<size_t>(bytes, 16));
+    H.table(d, std::max<size_t>(bytes, 16), s);
     if (bytes) MBL_HIP(hipMemcpyAsync(d.get(), src, bytes, hipMemcpyHostToDevice, s));
   };
   for (int ps = 0; ps < 2; ++ps) up(S.tiles[ps], tl[ps].data(), tl[ps].size() * sizeof(SplitTile));

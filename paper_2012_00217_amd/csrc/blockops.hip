@@ -301,6 +301,7 @@ template <class T>
 void launch_gram(int64_t n, const T* A, int64_t lda, int p, const T* B, int64_t ldb, int q,
                  double* C, int64_t ldc, hipStream_t s) {
   if (p == 0 || q == 0) return;
+  PhaseTick tick(PhaseClock::GRAM, s);
   // A^T A: only the upper tiles (the Rayleigh-Ritz and Cholesky-QR Grams)
   const int sym = (A == B && lda == ldb && p == q) ? 1 : 0;
   const int tq = (q + 63) / 64;

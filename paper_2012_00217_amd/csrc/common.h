@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <cstdint>
 #include <cstdio>
 #include <stdexcept>
@@ -37,35 +38,48 @@ struct Error : std::runtime_error {
 // Device allocation through the installed callback, else hipMallocAsync on
 // the stream (`ordered`: work buffers, freed stream-ordered so concurrent
 // solves never wait on a device-wide free) or hipMalloc (long-lived tables).
-void* dev_alloc(size_t bytes, hipStream_t s, bool ordered);
-void dev_free(void* p, hipStream_t s, bool ordered);
+// The allocator that served a buffer is recorded with it and frees it, so a
+// callback installed or removed in between never sees foreign pointers.
+struct AllocOwner {
+  mbl_free_fn free_fn = nullptr;  // callback that frees it, or nullptr (HIP)
+  void* ctx = nullptr;
+  bool ordered = true;            // HIP path: hipFreeAsync (else hipFree)
+  hipStream_t s = nullptr;        // stream handed to the free
+};
+void* dev_alloc(size_t bytes, hipStream_t s, bool ordered, AllocOwner* owner);
+void dev_free(void* p, const AllocOwner& owner);
 
 // Owning device buffer.
 class DevBuf {
  public:
   DevBuf() = default;
-  DevBuf(size_t bytes, hipStream_t s) : s_(s) { reset(bytes, s); }
+  DevBuf(size_t bytes, hipStream_t s) { reset(bytes, s); }
   ~DevBuf() { release(); }
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : p_(o.p_), n_(o.n_), s_(o.s_), ordered_(o.ordered_) {
+  DevBuf(DevBuf&& o) noexcept : p_(o.p_), n_(o.n_), own_(o.own_) {
     o.p_ = nullptr;
     o.n_ = 0;
   }
   DevBuf& operator=(DevBuf&& o) noexcept {
     if (this != &o) {
       release();
-      p_ = o.p_; n_ = o.n_; s_ = o.s_; ordered_ = o.ordered_;
+      p_ = o.p_; n_ = o.n_; own_ = o.own_;
       o.p_ = nullptr; o.n_ = 0;
     }
     return *this;
   }
-  // stream-ordered work buffer
+  // stream-ordered work buffer, freed on the same stream
   void reset(size_t bytes, hipStream_t s) { alloc(bytes, s, true); }
-  // long-lived buffer (outlives the stream it was made on)
+  // long-lived buffer (outlives the stream it was made on): hipMalloc/hipFree
   void reset_persistent(size_t bytes) { alloc(bytes, nullptr, false); }
+  // stream-ordered buffer freed on stream `release_on` (which must outlive it)
+  void reset_ordered(size_t bytes, hipStream_t s, hipStream_t release_on) {
+    alloc(bytes, s, true);
+    own_.s = release_on;
+  }
   void release() {
-    if (p_) dev_free(p_, s_, ordered_);
+    if (p_) dev_free(p_, own_);
     p_ = nullptr;
     n_ = 0;
   }
@@ -76,15 +90,12 @@ class DevBuf {
  private:
   void alloc(size_t bytes, hipStream_t s, bool ordered) {
     release();
-    s_ = s;
-    ordered_ = ordered;
-    if (bytes) p_ = dev_alloc(bytes, s, ordered);
+    if (bytes) p_ = dev_alloc(bytes, s, ordered, &own_);
     n_ = bytes;
   }
   void* p_ = nullptr;
   size_t n_ = 0;
-  hipStream_t s_ = nullptr;
-  bool ordered_ = true;
+  AllocOwner own_;
 };
 
 // One tile of the two-pass (split) apply.  The chain is cut between sites q-1
@@ -140,6 +151,16 @@ struct Ham {
   DevBuf diag;     // double [n]  <s|H|s>
   std::vector<uint32_t> pascal_host;
   SplitTables split;
+  // Stream the tables are allocated and freed on, stream-ordered (worker
+  // solves of the batch and the server), or nullptr: hipMalloc / hipFree
+  // after a device synchronisation (handles of the C ABI).
+  hipStream_t home = nullptr;
+  void table(DevBuf& d, size_t bytes, hipStream_t s) const {
+    if (home)
+      d.reset_ordered(bytes, s, home);
+    else
+      d.reset_persistent(bytes);
+  }
 };
 
 // Host Pascal table C[i][t] (row-major, 33 x 33), 0 where t > i.
@@ -211,10 +232,57 @@ struct PcgTiming {
   ~PcgTiming();
 };
 
-// PCG: W = PCG_m(R) (columns independent) with Jacobi diagonal jac.
+// Optional HIP-event timing of a solve's phases (mbl_solve_opts.timing):
+// plain applies, Gram products and the small dense kernels.  A solve installs
+// its clock for its own thread (t_phase_clock); the launchers of those kernels
+// bracket their launches with a PhaseTick, which does nothing when no clock is
+// installed.  collect() harvests finished pairs after a stream sync.
+struct PhaseClock {
+  enum { APPLY = 0, GRAM = 1, SMALL = 2 };
+  double ms[3] = {0, 0, 0};
+  struct Pair {
+    int kind;
+    hipEvent_t a, b;
+  };
+  std::vector<Pair> pend;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t get();
+  void collect();
+  ~PhaseClock();
+};
+extern thread_local PhaseClock* t_phase_clock;
+struct PhaseTick {
+  PhaseClock* c = nullptr;
+  int kind = 0;
+  hipEvent_t a = nullptr;
+  hipStream_t s = nullptr;
+  PhaseTick(int k, hipStream_t st);
+  ~PhaseTick();
+  PhaseTick(const PhaseTick&) = delete;
+  PhaseTick& operator=(const PhaseTick&) = delete;
+};
+
+// When a solve must stop early: a wall-clock deadline and/or a flag another
+// thread sets.  Checked between outer iterations and between chunks of
+// replayed CG steps.
+struct StopCheck {
+  bool has_deadline = false;
+  std::chrono::steady_clock::time_point deadline{};
+  const volatile int* flag = nullptr;
+  bool triggered() const {
+    if (flag && *flag != 0) return true;
+    return has_deadline && std::chrono::steady_clock::now() >= deadline;
+  }
+};
+
+// PCG: W = PCG_m(R) (columns independent) with Jacobi diagonal jac.  The
+// leading `keep` columns run max(m, m_keep) steps, the others m (keep < 0: all
+// run m).  With a stop check, fewer steps may run (W is then the CG iterate
+// reached).
 template <class T>
 void run_pcg(const Ham& H, double sigma, const T* jac, const T* R, int64_t ldr, T* W, int64_t ldw,
-             int b, int m, hipStream_t s, PcgTiming* tm = nullptr);
+             int b, int m, hipStream_t s, PcgTiming* tm = nullptr,
+             const StopCheck* stop = nullptr, int keep = -1, int m_keep = 0);
 
 // Jacobi diagonal of the fold, d = (E - sigma)^2 + (J/2)^2 * (#active bonds).
 template <class T>
@@ -258,8 +326,10 @@ mbl_status solve_interior(const Ham& H, double sigma, int nev, int b, double tol
                           double* resid, mbl_solve_info* info, hipStream_t s);
 mbl_status spectrum_bounds(const Ham& H, double tol, double* emin, double* emax, hipStream_t s);
 
-// Validated construction of a sector handle (throws Error on bad input).
-Ham* create_ham(int L, double Sz, double J, double Delta, const double* h_host, hipStream_t s);
+// Validated construction of a sector handle (throws Error on bad input);
+// home: see Ham::home.
+Ham* create_ham(int L, double Sz, double J, double Delta, const double* h_host, hipStream_t s,
+                hipStream_t home = nullptr);
 // Sector dimension C(L, Sz + L/2) (throws Error for a sector that does not exist).
 int64_t sector_dim(int L, double Sz);
 
@@ -267,7 +337,8 @@ int64_t sector_dim(int L, double Sz);
 size_t solve_footprint(int L, double Sz, int b, int prec);
 mbl_status batch_solve(int count, const mbl_problem* probs, mbl_result* res, int conc);
 struct Server;
-mbl_status server_create(int conc, size_t budget, Server** out);
+mbl_status server_create(int device, int conc, size_t budget, Server** out);
+mbl_status server_cancel(Server* srv, uint64_t ticket);
 mbl_status server_submit(Server* srv, const mbl_problem* rq, uint64_t* ticket);
 mbl_status server_wait(Server* srv, uint64_t ticket, double timeout_s, mbl_result* out);
 mbl_status server_stats(Server* srv, mbl_server_stats* st);

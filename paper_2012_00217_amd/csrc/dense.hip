@@ -324,36 +324,6 @@ __global__ __launch_bounds__(256) void k_small_gemm(int M, int N, int K, double 
   C[(int64_t)i * ldc + j] = alpha * s + (beta == 0.0 ? 0.0 : beta * C[(int64_t)i * ldc + j]);
 }
 
-// Pick the nev Ritz values with smallest |theta| (ties: lower index), output
-// their indices in ascending theta.  theta is ascending on input.
-__global__ void k_select_nearest(int b, int nev, const double* __restrict__ theta,
-                                 int* __restrict__ sel) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  // theta ascending: the nearest-to-zero set is a contiguous window
-  int lo = 0, hi = 0;  // window [lo, hi)
-  int best = 0;
-  double bestv = fabs(theta[0]);
-  for (int j = 1; j < b; ++j)
-    if (fabs(theta[j]) < bestv) {
-      bestv = fabs(theta[j]);
-      best = j;
-    }
-  lo = best;
-  hi = best + 1;
-  while (hi - lo < nev) {
-    if (lo == 0) {
-      ++hi;
-    } else if (hi == b) {
-      --lo;
-    } else if (fabs(theta[lo - 1]) <= fabs(theta[hi])) {
-      --lo;
-    } else {
-      ++hi;
-    }
-  }
-  for (int j = 0; j < nev; ++j) sel[j] = lo + j;
-}
-
 __global__ __launch_bounds__(256) void k_gather_cols(int rows, int nsel, const int* __restrict__ sel,
                                                      const double* __restrict__ Z, int64_t ldz,
                                                      double* __restrict__ out, int64_t ldo) {
@@ -374,6 +344,7 @@ size_t small_eigh_work_bytes(int m) {
 
 void small_eigh(int m, const double* A, int64_t lda, double* w, double* V, int64_t ldv,
                 double* work, hipStream_t s) {
+  PhaseTick tick(PhaseClock::SMALL, s);
   if (m <= 0) return;
   const int mm = m + (m & 1);
   const int max_sweeps = 30;
@@ -435,6 +406,7 @@ void small_eigh(int m, const double* A, int64_t lda, double* w, double* V, int64
 // Cholesky-with-dropping of a b x b Gram; returns the number of kept columns.
 int chol_drop(int b, const double* G, int64_t ldg, double tol, double* Rinv, double* work,
               int* dcount, hipStream_t s) {
+  PhaseTick tick(PhaseClock::SMALL, s);
   if (b <= 0) return 0;
   if (b > 1024) fail(MBL_EINVAL, "chol_drop: b > 1024");
   const int in_lds = b <= kCholLds;
@@ -454,16 +426,13 @@ int chol_drop(int b, const double* G, int64_t ldg, double tol, double* Rinv, dou
 void small_gemm(int M, int N, int K, double alpha, const double* A, int64_t lda, bool ta,
                 const double* B, int64_t ldb, bool tb, double beta, double* C, int64_t ldc,
                 hipStream_t s) {
+  PhaseTick tick(PhaseClock::SMALL, s);
   if ((int64_t)M * N == 0) return;
   hipLaunchKernelGGL(k_small_gemm, dim3(g1((int64_t)M * N)), dim3(256), 0, s, M, N, K, alpha, A,
                      lda, (int)ta, B, ldb, (int)tb, beta, C, ldc);
   MBL_CHECK_LAUNCH();
 }
 
-void select_nearest(int b, int nev, const double* theta, int* sel, hipStream_t s) {
-  hipLaunchKernelGGL(k_select_nearest, dim3(1), dim3(64), 0, s, b, nev, theta, sel);
-  MBL_CHECK_LAUNCH();
-}
 
 void gather_cols(int rows, int nsel, const int* sel, const double* Z, int64_t ldz, double* out,
                  int64_t ldo, hipStream_t s) {

@@ -35,6 +35,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <utility>
 #include <vector>
 
@@ -47,9 +48,67 @@ int chol_drop(int b, const double* G, int64_t ldg, double tol, double* Rinv, dou
 void small_gemm(int M, int N, int K, double alpha, const double* A, int64_t lda, bool ta,
                 const double* B, int64_t ldb, bool tb, double beta, double* C, int64_t ldc,
                 hipStream_t s);
-void select_nearest(int b, int nev, const double* theta, int* sel, hipStream_t s);
 void gather_cols(int rows, int nsel, const int* sel, const double* Z, int64_t ldz, double* out,
                  int64_t ldo, hipStream_t s);
+
+thread_local PhaseClock* t_phase_clock = nullptr;
+
+hipEvent_t PhaseClock::get() {
+  if (!pool.empty()) {
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  MBL_HIP(hipEventCreate(&e));
+  return e;
+}
+
+void PhaseClock::collect() {
+  for (const Pair& p : pend) {
+    float t = 0.f;
+    if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&t, p.a, p.b) == hipSuccess)
+      ms[p.kind] += t;
+    pool.push_back(p.a);
+    pool.push_back(p.b);
+  }
+  pend.clear();
+}
+
+PhaseClock::~PhaseClock() {
+  for (const Pair& p : pend) {
+    (void)hipEventSynchronize(p.b);
+    pool.push_back(p.a);
+    pool.push_back(p.b);
+  }
+  for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+}
+
+PhaseTick::PhaseTick(int k, hipStream_t st) : c(t_phase_clock), kind(k), s(st) {
+  if (!c) return;
+  a = c->get();
+  if (hipEventRecord(a, s) != hipSuccess) {
+    c->pool.push_back(a);
+    c = nullptr;
+  }
+}
+
+PhaseTick::~PhaseTick() {
+  if (!c) return;
+  hipEvent_t b = nullptr;
+  try {
+    b = c->get();
+  } catch (...) {
+    c->pool.push_back(a);
+    return;
+  }
+  if (hipEventRecord(b, s) == hipSuccess) {
+    c->pend.push_back({kind, a, b});
+  } else {
+    c->pool.push_back(a);
+    c->pool.push_back(b);
+  }
+}
 
 namespace {
 
@@ -68,10 +127,14 @@ struct Params {
   double sign = 1.0;
   bool diag_precond = false;  // plain mode: W = R / |sign*diag(H) - mu| instead of W = R
   double lock_tol = 0;        // > 0: soft locking of wanted pairs with residual <= lock_tol
+  StopCheck stop;             // deadline / cancel flag of the caller
+  bool fold_select = true;    // fold: wanted pairs by their fold quotient (Phase::check)
+  double guard_frac = 1.0;    // CG steps of the guard columns, as a fraction of m
 };
 
 struct Stats {
   int iters = 0, iters_fp64 = 0;
+  bool stopped = false;  // the caller's deadline or cancel flag ended the solve
   int64_t applies = 0, pcg_steps = 0, pcg_columns = 0;
   double t_pcg = 0, t_rr = 0;
   bool timing = false;
@@ -250,54 +313,72 @@ class Phase {
     launch_gram<TB>(n, X, B_.ld, b, HX, B_.ld, b, K, b, s_);
     if (p_.sign != 1.0) small_gemm(b, b, 0, 0.0, K, b, false, K, b, false, p_.sign, K, b, s_);
     small_eigh(b, K, b, sm_.th.as<double>(), sm_.Z.as<double>(), b, sm_.ew.as<double>(), s_);
-    if (p_.fold) {
-      select_nearest(b, nev, sm_.th.as<double>(), sm_.sel.as<int>(), s_);
-    } else {
-      std::vector<int> sel(nev);
-      for (int j = 0; j < nev; ++j) sel[j] = j;
-      MBL_HIP(hipMemcpyAsync(sm_.sel.get(), sel.data(), nev * sizeof(int), hipMemcpyHostToDevice,
-                             s_));
-    }
-    gather_cols(b, nev, sm_.sel.as<int>(), sm_.Z.as<double>(), b, sm_.Zs.as<double>(), nev, s_);
     std::vector<double> th_all(b);
-    std::vector<int> sel(nev);
     MBL_HIP(hipMemcpyAsync(th_all.data(), sm_.th.as<double>(), b * sizeof(double),
                            hipMemcpyDeviceToHost, s_));
-    MBL_HIP(hipMemcpyAsync(sel.data(), sm_.sel.as<int>(), nev * sizeof(int), hipMemcpyDeviceToHost,
-                           s_));
     MBL_HIP(hipStreamSynchronize(s_));
-    theta.resize(nev);
-    for (int j = 0; j < nev; ++j) theta[j] = th_all[sel[j]];
-    // residual block: sign*HX Zs - X Zs diag(theta)
+    last_theta_all_ = th_all;
+    // residuals of all b H-Ritz pairs: R = sign*HX Z - X Z diag(theta)
     double* Zt = sm_.T1.as<double>();
-    MBL_HIP(hipMemcpyAsync(Zt, sm_.Zs.as<double>(), (size_t)b * nev * sizeof(double),
+    MBL_HIP(hipMemcpyAsync(Zt, sm_.Z.as<double>(), (size_t)b * b * sizeof(double),
                            hipMemcpyDeviceToDevice, s_));
-    {
-      std::vector<double> D((size_t)nev * nev, 0.0);
-      for (int j = 0; j < nev; ++j) D[(size_t)j * nev + j] = -theta[j];
-      MBL_HIP(hipMemcpyAsync(sm_.T2.get(), D.data(), D.size() * sizeof(double),
-                             hipMemcpyHostToDevice, s_));
-      small_gemm(b, nev, nev, 1.0, sm_.Zs.as<double>(), nev, false, sm_.T2.as<double>(), nev,
-                 false, 0.0, Zt, nev, s_);
-    }
+    h_Dc_.assign((size_t)b * b, 0.0);
+    for (int j = 0; j < b; ++j) h_Dc_[(size_t)j * b + j] = -th_all[j];
+    MBL_HIP(hipMemcpyAsync(sm_.T2.get(), h_Dc_.data(), h_Dc_.size() * sizeof(double),
+                           hipMemcpyHostToDevice, s_));
+    small_gemm(b, b, b, 1.0, sm_.Z.as<double>(), b, false, sm_.T2.as<double>(), b, false, 0.0, Zt, b,
+               s_);
     TB* Rr = B_.tmp.template as<TB>();
     if (p_.sign != 1.0) {
       double* Zsg = sm_.Ch.as<double>();
-      MBL_HIP(hipMemcpyAsync(Zsg, sm_.Zs.as<double>(), (size_t)b * nev * sizeof(double),
+      MBL_HIP(hipMemcpyAsync(Zsg, sm_.Z.as<double>(), (size_t)b * b * sizeof(double),
                              hipMemcpyDeviceToDevice, s_));
-      small_gemm(b, nev, 0, 0.0, Zsg, nev, false, Zsg, nev, false, p_.sign, Zsg, nev, s_);
-      launch_combine<TB>(n, HX, B_.ld, b, Zsg, nev, Rr, b, nev, 0.0, s_);
+      small_gemm(b, b, 0, 0.0, Zsg, b, false, Zsg, b, false, p_.sign, Zsg, b, s_);
+      launch_combine<TB>(n, HX, B_.ld, b, Zsg, b, Rr, b, b, 0.0, s_);
     } else {
-      launch_combine<TB>(n, HX, B_.ld, b, sm_.Zs.as<double>(), nev, Rr, b, nev, 0.0, s_);
+      launch_combine<TB>(n, HX, B_.ld, b, sm_.Z.as<double>(), b, Rr, b, b, 0.0, s_);
     }
-    launch_combine<TB>(n, X, B_.ld, b, Zt, nev, Rr, b, nev, 1.0, s_);
-    launch_gram<TB>(n, Rr, b, nev, Rr, b, nev, sm_.K.as<double>(), nev, s_);
-    std::vector<double> G((size_t)nev * nev);
+    launch_combine<TB>(n, X, B_.ld, b, Zt, b, Rr, b, b, 1.0, s_);
+    launch_gram<TB>(n, Rr, b, b, Rr, b, b, sm_.K.as<double>(), b, s_);
+    std::vector<double> G((size_t)b * b);
     MBL_HIP(hipMemcpyAsync(G.data(), sm_.K.as<double>(), G.size() * sizeof(double),
                            hipMemcpyDeviceToHost, s_));
     MBL_HIP(hipStreamSynchronize(s_));
+    std::vector<double> r_all(b);
+    for (int j = 0; j < b; ++j) r_all[j] = std::sqrt(std::max(0.0, G[(size_t)j * b + j]));
+    // The wanted pairs.  Fold: the nev H-Ritz pairs whose vectors x have the
+    // smallest fold quotient x^T (H - sigma)^2 x = theta^2 + |r|^2 (r is
+    // orthogonal to x).  Selecting by |theta| alone would let an unconverged
+    // combination whose H-quotient happens to lie near sigma -- the middle of
+    // the spectrum, where such quotients cluster -- take the place of a true
+    // eigenvalue at the edge of the window; its fold quotient gives it away.
+    // Once the pairs converge (r -> 0) both rules agree.  Plain mode: the nev
+    // smallest theta of sign*(H - sigma).
+    std::vector<int> sel(nev);
+    {
+      std::vector<int> ord(b);
+      for (int j = 0; j < b; ++j) ord[j] = j;
+      if (p_.fold) {
+        auto key = [&](int j) {
+          return p_.fold_select ? th_all[j] * th_all[j] + r_all[j] * r_all[j] : std::fabs(th_all[j]);
+        };
+        std::stable_sort(ord.begin(), ord.end(), [&](int a, int c) { return key(a) < key(c); });
+        ord.resize(nev);
+        std::sort(ord.begin(), ord.end(), [&](int a, int c) { return th_all[a] < th_all[c]; });
+      }
+      for (int j = 0; j < nev; ++j) sel[j] = ord[j];
+    }
+    h_sel_ = sel;
+    MBL_HIP(hipMemcpyAsync(sm_.sel.get(), h_sel_.data(), nev * sizeof(int), hipMemcpyHostToDevice,
+                           s_));
+    gather_cols(b, nev, sm_.sel.as<int>(), sm_.Z.as<double>(), b, sm_.Zs.as<double>(), nev, s_);
+    theta.resize(nev);
     res.resize(nev);
-    for (int j = 0; j < nev; ++j) res[j] = std::sqrt(std::max(0.0, G[(size_t)j * nev + j]));
+    for (int j = 0; j < nev; ++j) {
+      theta[j] = th_all[sel[j]];
+      res[j] = r_all[sel[j]];
+    }
+    MBL_HIP(hipStreamSynchronize(s_));
     // soft locking: H-Ritz directions (columns of Z) of the wanted pairs
     // below the locking tolerance, most converged first
     locked_.clear();
@@ -324,77 +405,85 @@ class Phase {
     TB* S = B_.S[cur_].template as<TB>();
     TB* HS = B_.HS[cur_].template as<TB>();
     TB* R = B_.R.template as<TB>();
-    // A-residual R = sign*(op) applied to HX minus X diag(mu)
-    {
-      const auto t0 = clk::now();
-      std::vector<double> D((size_t)b * b, 0.0);
-      for (int j = 0; j < b; ++j) D[(size_t)j * b + j] = -mu_[j];
-      MBL_HIP(hipMemcpyAsync(sm_.T2.get(), D.data(), D.size() * sizeof(double),
-                             hipMemcpyHostToDevice, s_));
-      if (p_.fold) {
-        apply(HS, B_.ld, R, b, b);
-      } else {
-        // R = sign * HX
-        std::vector<double> I((size_t)b * b, 0.0);
-        for (int j = 0; j < b; ++j) I[(size_t)j * b + j] = p_.sign;
-        MBL_HIP(hipMemcpyAsync(sm_.T1.get(), I.data(), I.size() * sizeof(double),
-                               hipMemcpyHostToDevice, s_));
-        launch_combine<TB>(n, HS, B_.ld, b, sm_.T1.as<double>(), b, R, b, b, 0.0, s_);
-      }
-      launch_combine<TB>(n, S, B_.ld, b, sm_.T2.as<double>(), b, R, b, b, 1.0, s_);
-      MBL_HIP(hipStreamSynchronize(s_));
-      st_.t_rr += secs(t0);
-    }
     TB* W = S + b + bp_;
     const int64_t ld = B_.ld;
-    // Soft locking: wanted pairs already below the locking tolerance get no
-    // new direction.  R is rotated into the H-Ritz basis of span(X) (Z from
-    // check(); R Z is the residual block of those Ritz vectors up to a part
-    // inside span(X), which the orthogonalisation below removes), the locked
-    // columns are left out, and the active width is rounded up to whole
-    // 128-byte rows of the preconditioner's scalars, keeping the least
-    // converged locked pairs active, so the block CG keeps its tuned shapes.
     int wq = b;
     const TB* Rin = R;
     int64_t ldRin = b;
-    if (p_.fold && m > 0 && !locked_.empty()) {
-      const int grain = 128 / (int)sizeof(TP);
-      int keep = b - (int)locked_.size();
-      keep = std::min(b, std::max(grain, (keep + grain - 1) / grain * grain));
-      if (keep < b) {
-        std::vector<char> drop(b, 0);
+    // Columns that get a new direction: all, or with soft locking all but the
+    // most converged locked wanted pairs (Z columns), the active width rounded
+    // up to whole 128-byte rows of the preconditioner's scalars so the block
+    // CG keeps its tuned shapes.
+    std::vector<int>& act = h_act_;
+    act.clear();
+    {
+      std::vector<char> drop(b, 0);
+      if (p_.fold && m > 0 && !locked_.empty()) {
+        const int grain = 128 / (int)sizeof(TP);
+        int keep = b - (int)locked_.size();
+        keep = std::min(b, std::max(grain, (keep + grain - 1) / grain * grain));
         for (int k = 0; k < b - keep; ++k) drop[locked_[k]] = 1;
-        std::vector<int> act;
-        for (int j = 0; j < b; ++j)
-          if (!drop[j]) act.push_back(j);
-        MBL_HIP(hipMemcpyAsync(sm_.asel.get(), act.data(), keep * sizeof(int),
-                               hipMemcpyHostToDevice, s_));
-        gather_cols(b, keep, sm_.asel.as<int>(), sm_.Z.as<double>(), b, sm_.Za.as<double>(), keep,
-                    s_);
-        TB* Rt = B_.tmp.template as<TB>();
-        launch_combine<TB>(n, R, b, b, sm_.Za.as<double>(), keep, Rt, keep, keep, 0.0, s_);
-        MBL_HIP(hipStreamSynchronize(s_));  // act is a host temporary
-        Rin = Rt;
-        ldRin = keep;
-        wq = keep;
       }
+      for (int j = 0; j < b; ++j)
+        if (!drop[j]) act.push_back(j);
     }
+    const int keep = (int)act.size();
+    const auto t_res = clk::now();
+    // A-residual R = sign*(op) applied to HX minus X diag(mu)
+    h_D_.assign((size_t)b * b, 0.0);
+    for (int j = 0; j < b; ++j) h_D_[(size_t)j * b + j] = -mu_[j];
+    MBL_HIP(hipMemcpyAsync(sm_.T2.get(), h_D_.data(), h_D_.size() * sizeof(double),
+                           hipMemcpyHostToDevice, s_));
+    if (p_.fold) {
+      apply(HS, B_.ld, R, b, b);
+    } else {
+      // R = sign * HX
+      h_I_.assign((size_t)b * b, 0.0);
+      for (int j = 0; j < b; ++j) h_I_[(size_t)j * b + j] = p_.sign;
+      MBL_HIP(hipMemcpyAsync(sm_.T1.get(), h_I_.data(), h_I_.size() * sizeof(double),
+                             hipMemcpyHostToDevice, s_));
+      launch_combine<TB>(n, HS, B_.ld, b, sm_.T1.as<double>(), b, R, b, b, 0.0, s_);
+    }
+    launch_combine<TB>(n, S, B_.ld, b, sm_.T2.as<double>(), b, R, b, b, 1.0, s_);
+    if (p_.fold && m > 0 && keep < b) {
+      TB* Rt = B_.tmp.template as<TB>();
+      MBL_HIP(hipMemcpyAsync(sm_.asel.get(), act.data(), keep * sizeof(int),
+                             hipMemcpyHostToDevice, s_));
+      gather_cols(b, keep, sm_.asel.as<int>(), sm_.Z.as<double>(), b, sm_.Za.as<double>(), keep,
+                  s_);
+      launch_combine<TB>(n, R, b, b, sm_.Za.as<double>(), keep, Rt, keep, keep, 0.0, s_);
+      Rin = Rt;
+      ldRin = keep;
+      wq = keep;
+    }
+    MBL_HIP(hipStreamSynchronize(s_));
+    st_.t_rr += secs(t_res);
     if (p_.fold && m > 0) {
       const auto t0 = clk::now();
       PcgTiming* tm = st_.timing ? &st_.tm[sizeof(TP) == 4 ? 1 : 0] : nullptr;
+      const StopCheck* stop = (p_.stop.has_deadline || p_.stop.flag) ? &p_.stop : nullptr;
+      // guard columns (beyond the nev smallest fold Ritz values, which lead R
+      // in its A-Ritz order) may stop after a fraction of the CG steps
+      int m_all = m, keep = -1;
+      if (p_.guard_frac < 1.0 && Rin == R && p_.nev < wq) {
+        m_all = std::max(1, (int)std::lround(p_.guard_frac * m));
+        keep = p_.nev;
+      }
       if constexpr (std::is_same<TB, TP>::value) {
-        run_pcg<TP>(H_, p_.sigma, jac, Rin, ldRin, W, ld, wq, m, s_, tm);
+        run_pcg<TP>(H_, p_.sigma, jac, Rin, ldRin, W, ld, wq, m_all, s_, tm, stop, keep, m);
         MBL_HIP(hipStreamSynchronize(s_));
       } else {
         DevBuf rp((size_t)n * wq * sizeof(TP), s_), wp((size_t)n * wq * sizeof(TP), s_);
         launch_convert<TB, TP>(n, wq, Rin, ldRin, rp.as<TP>(), wq, s_);
-        run_pcg<TP>(H_, p_.sigma, jac, rp.as<TP>(), wq, wp.as<TP>(), wq, wq, m, s_, tm);
+        run_pcg<TP>(H_, p_.sigma, jac, rp.as<TP>(), wq, wp.as<TP>(), wq, wq, m_all, s_, tm, stop,
+                    keep, m);
         launch_convert<TP, TB>(n, wq, wp.as<TP>(), wq, W, ld, s_);
         MBL_HIP(hipStreamSynchronize(s_));
       }
       st_.applies += 2LL * m;
       st_.pcg_steps += m;
-      st_.pcg_columns += (int64_t)m * wq;
+      st_.pcg_columns += keep < 0 ? (int64_t)m * wq
+                                  : (int64_t)m_all * wq + (int64_t)(m - m_all) * keep;
       st_.t_pcg += secs(t0);
     } else if constexpr (std::is_same<TB, double>::value) {
       if (!p_.fold && p_.diag_precond) {
@@ -441,6 +530,9 @@ class Phase {
     }
   }
 
+  // Ritz values of all b columns from the last check() (verbose diagnostics).
+  const std::vector<double>& theta_all() const { return last_theta_all_; }
+
   TB* X() { return B_.S[cur_].template as<TB>(); }
   int64_t ldx() const { return B_.ld; }
   const std::vector<double>& mu() const { return mu_; }
@@ -456,7 +548,47 @@ class Phase {
   int bp_ = 0;
   std::vector<double> mu_;
   std::vector<int> locked_;  // Z columns of locked wanted pairs, most converged first
+  std::vector<double> last_theta_all_;
+  // host sources of small uploads: members, so that each outlives its
+  // asynchronous copy (every upload is followed by a stream synchronisation
+  // before the member is written again)
+  std::vector<double> h_D_, h_I_, h_Dc_;
+  std::vector<int> h_act_, h_sel_;
 };
+
+// verbose >= 2: where the wanted pairs stand.  Counts of residuals below
+// 1e-4 / 1e-6 / 1e-8 / 1e-10, the ranks (by distance to sigma, 0 = nearest)
+// and residuals of the four worst pairs, and the distances to sigma of the
+// farthest wanted Ritz value and of the nearest unwanted ones.
+void print_detail(const char* tag, int iter, const std::vector<double>& theta,
+                  const std::vector<double>& res, const std::vector<double>& th_all) {
+  const int nev = (int)theta.size();
+  std::vector<int> ord(nev);
+  for (int j = 0; j < nev; ++j) ord[j] = j;
+  std::sort(ord.begin(), ord.end(),
+            [&](int a, int b) { return std::fabs(theta[a]) < std::fabs(theta[b]); });
+  std::vector<int> rank(nev);
+  for (int r = 0; r < nev; ++r) rank[ord[r]] = r;
+  int c4 = 0, c6 = 0, c8 = 0, c10 = 0;
+  for (double r : res) {
+    c4 += r <= 1e-4;
+    c6 += r <= 1e-6;
+    c8 += r <= 1e-8;
+    c10 += r <= 1e-10;
+  }
+  std::vector<int> worst(nev);
+  for (int j = 0; j < nev; ++j) worst[j] = j;
+  std::sort(worst.begin(), worst.end(), [&](int a, int b) { return res[a] > res[b]; });
+  std::vector<double> d;
+  for (double t : th_all) d.push_back(std::fabs(t));
+  std::sort(d.begin(), d.end());
+  std::fprintf(stderr, "[mbl %s detail] iter %d below 1e-4/6/8/10: %d %d %d %d; worst (rank:resid)", tag,
+               iter, c4, c6, c8, c10);
+  for (int k = 0; k < std::min(4, nev); ++k)
+    std::fprintf(stderr, " %d:%.2e", rank[worst[k]], res[worst[k]]);
+  std::fprintf(stderr, "; |theta| wanted max %.3e, next %.3e %.3e\n", d[nev - 1],
+               (int)d.size() > nev ? d[nev] : 0.0, (int)d.size() > nev + 1 ? d[nev + 1] : 0.0);
+}
 
 // Fresh FP64 residuals of V (n x nev) with values theta (of H - sigma).
 std::vector<double> fresh_residuals(const Ham& H, double sigma, const double* V, int64_t ldv,
@@ -500,6 +632,7 @@ bool run_phase(Phase<TB>& ph, const TP* jac, const Params& p, double stop_tol, i
   int since = 0;
   while (true) {
     ph.check(theta, res);
+    if (t_phase_clock) t_phase_clock->collect();  // check() synchronised the stream
     const double r = maxv(res);
     if (p.verbose) {
       if (p.lock_tol > 0)
@@ -508,8 +641,13 @@ bool run_phase(Phase<TB>& ph, const TP* jac, const Params& p, double stop_tol, i
       else
         std::fprintf(stderr, "[mbl %s] iter %d applies %lld max_resid %.3e\n", tag, st.iters,
                      (long long)st.applies, r);
+      if (p.verbose >= 2) print_detail(tag, st.iters, theta, res, ph.theta_all());
     }
     if (r <= stop_tol) return true;
+    if (p.stop.triggered()) {
+      st.stopped = true;
+      return false;
+    }
     if (patience > 0) {
       if (r < gain * best) {
         best = r;
@@ -542,8 +680,27 @@ mbl_status solve_interior(const Ham& H, double sigma, int nev, int b, double tol
   p.verbose = o.verbose;
   p.seed = o.seed;
   p.lock_tol = o.lock ? 0.1 * tol : 0.0;
+  // MBL_SELECT=theta: wanted pairs by |theta| alone (for comparison)
+  {
+    const char* sel = std::getenv("MBL_SELECT");
+    p.fold_select = !(sel && sel[0] == 't');
+  }
+  p.guard_frac = o.guard_cg > 0 ? std::min(1.0, o.guard_cg) : (H.n >= 500000 ? 0.1 : 1.0);
+  p.stop.flag = o.cancel;
+  if (o.max_seconds > 0) {
+    p.stop.has_deadline = true;
+    p.stop.deadline = t_start + std::chrono::duration_cast<clk::duration>(
+                                    std::chrono::duration<double>(o.max_seconds));
+  }
   Stats st;
   st.timing = o.timing != 0;
+  // phase clock of this solve (this thread) while the solve runs
+  PhaseClock clock;
+  struct ClockScope {
+    PhaseClock* prev;
+    explicit ClockScope(PhaseClock* c) : prev(t_phase_clock) { t_phase_clock = c; }
+    ~ClockScope() { t_phase_clock = prev; }
+  } clock_scope(st.timing ? &clock : nullptr);
   Small sm(b, s);
   const int64_t n = H.n;
   const int prec = o.precision;
@@ -598,7 +755,7 @@ mbl_status solve_interior(const Ham& H, double sigma, int nev, int b, double tol
       ph.vectors(V.as<double>(), nev);
       res = fresh_residuals(H, sigma, V.as<double>(), nev, nev, theta, st, s);
       ok = reached && maxv(res) <= tol;
-      if (ok || !reached || iters_left <= 0) break;
+      if (ok || !reached || iters_left <= 0 || st.stopped) break;
       // tracked residuals passed but fresh ones did not: one more step, with
       // every direction active
       ph.unlock();
@@ -622,6 +779,7 @@ mbl_status solve_interior(const Ham& H, double sigma, int nev, int b, double tol
     MBL_HIP(hipMemcpy2DAsync(evecs, ldv * sizeof(double), V.get(), nev * sizeof(double),
                              nev * sizeof(double), n, hipMemcpyDeviceToDevice, s));
   MBL_HIP(hipStreamSynchronize(s));
+  if (st.timing) clock.collect();
   if (info) {
     info->iters = st.iters;
     info->iters_fp64 = st.iters_fp64;
@@ -642,9 +800,14 @@ mbl_status solve_interior(const Ham& H, double sigma, int nev, int b, double tol
       info->cg_apply2_ms[k] = st.tm[k].ms[1];
       info->cg_apply1_bytes[k] = st.tm[k].bytes[0];
       info->cg_apply2_bytes[k] = st.tm[k].bytes[1];
+      if (st.tm[k].split) info->cg_split = 1;
     }
+    info->t_apply = 1e-3 * clock.ms[PhaseClock::APPLY];
+    info->t_gram = 1e-3 * clock.ms[PhaseClock::GRAM];
+    info->t_small = 1e-3 * clock.ms[PhaseClock::SMALL];
   }
-  return ok ? MBL_OK : MBL_ENOCONV;
+  if (ok) return MBL_OK;
+  return st.stopped ? MBL_ECANCELLED : MBL_ENOCONV;
 }
 
 // Extreme eigenvalues by plain LOBPCG on +H and -H (block 4, no preconditioner).

@@ -107,11 +107,11 @@ inline unsigned grid1(int64_t n, int bs = 256) { return (unsigned)((n + bs - 1) 
 
 void build_tables(Ham& H, hipStream_t s) {
   H.pascal_host = pascal_table();
-  H.pascal.reset_persistent(H.pascal_host.size() * sizeof(uint32_t));
+  H.table(H.pascal, H.pascal_host.size() * sizeof(uint32_t), s);
   MBL_HIP(hipMemcpyAsync(H.pascal.get(), H.pascal_host.data(), H.pascal.bytes(),
                          hipMemcpyHostToDevice, s));
-  H.states.reset_persistent((size_t)H.n * sizeof(uint32_t));
-  H.diag.reset_persistent((size_t)H.n * sizeof(double));
+  H.table(H.states, (size_t)H.n * sizeof(uint32_t), s);
+  H.table(H.diag, (size_t)H.n * sizeof(double), s);
   hipLaunchKernelGGL(k_unrank, dim3(grid1(H.n)), dim3(256), 0, s, H.states.as<uint32_t>(), H.n,
                      H.L, H.nup, H.pascal.as<uint32_t>());
   MBL_CHECK_LAUNCH();

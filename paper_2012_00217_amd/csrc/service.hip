@@ -36,10 +36,10 @@ size_t footprint(int64_t n, int b, int prec) {
   // LOBPCG: S and HS double-buffered (4 x 3b columns), residual and scratch
   // (2b), starting block and eigenvectors (2b, FP64); PCG: r, p, T (3b) plus
   // the converted right-hand side and solution (2b) when the PCG runs in a
-  // narrower type; per row: state (4 B), diagonal (8 + 4 B), Jacobi (8 B).
+  // narrower type; per row: state (4 B), diagonal (8 B), Jacobi (8 B).
   auto phase = [&](int sb, int sp) {
     double cols = 14.0 * b * sb + 3.0 * b * sp + (sb != sp ? 2.0 * b * sp : 0.0);
-    return cols + 16.0 * b + 24.0;
+    return cols + 16.0 * b + 20.0;
   };
   double per_row = 0;
   if (prec == MBL_F64) per_row = phase(8, 8);
@@ -61,6 +61,7 @@ struct Job {
   std::vector<double> evals, resid;
   DevBuf V;  // server: eigenvectors kept until wait()
   int64_t n = 0;
+  volatile int cancel = 0;  // set by mbl_server_cancel while the solve runs
 };
 
 // One complete solve of a problem on stream s.  Writes evals/resid into the
@@ -70,7 +71,9 @@ void run_problem(Job& j, double* evecs, int64_t ldv, hipStream_t s) {
   mbl_result& r = j.r;
   try {
     const mbl_problem& p = j.p;
-    std::unique_ptr<Ham> H(create_ham(p.L, p.Sz, p.J, p.Delta, j.h.data(), s));
+    // tables stream-ordered on the worker's stream: freeing them never waits
+    // for the other workers' work
+    std::unique_ptr<Ham> H(create_ham(p.L, p.Sz, p.J, p.Delta, j.h.data(), s, s));
     j.n = H->n;
     if (p.nev < 1 || p.nev > p.block || 2 * (int64_t)p.block > H->n || p.block > 320 ||
         !(p.tol > 0) || !std::isfinite(p.tol))
@@ -90,6 +93,7 @@ void run_problem(Job& j, double* evecs, int64_t ldv, hipStream_t s) {
     // MBL_VERBOSE=1: one stderr line per outer iteration of every solve
     const char* verbose = std::getenv("MBL_VERBOSE");
     o.verbose = verbose ? std::atoi(verbose) : 0;
+    o.cancel = &j.cancel;
     if (o.precision != MBL_F64 && o.precision != MBL_MIXED && o.precision != MBL_PCG32)
       fail(MBL_EINVAL, "bad precision");
     j.evals.assign(p.nev, 0.0);
@@ -230,7 +234,8 @@ struct Server {
       if (j->p.want_vectors) {
         try {
           const int64_t n = sector_dim(j->p.L, j->p.Sz);
-          j->V.reset_persistent((size_t)n * std::max(1, j->p.nev) * sizeof(double));
+          // freed on the copy stream once wait() has copied it out
+          j->V.reset_ordered((size_t)n * std::max(1, j->p.nev) * sizeof(double), s, copy);
           vec = j->V.as<double>();
         } catch (const Error& e) {
           j->r.status = e.status;
@@ -255,9 +260,10 @@ struct Server {
   }
 };
 
-mbl_status server_create(int conc, size_t budget, Server** out) {
+mbl_status server_create(int device, int conc, size_t budget, Server** out) {
   auto srv = std::make_unique<Server>();
-  MBL_HIP(hipGetDevice(&srv->dev));
+  srv->dev = device;
+  MBL_HIP(hipSetDevice(device));
   if (budget == 0) {
     size_t fr = 0, tot = 0;
     MBL_HIP(hipMemGetInfo(&fr, &tot));
@@ -325,6 +331,28 @@ mbl_status server_wait(Server* srv, uint64_t ticket, double timeout_s, mbl_resul
   return MBL_OK;
 }
 
+mbl_status server_cancel(Server* srv, uint64_t ticket) {
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    auto it = srv->jobs.find(ticket);
+    if (it == srv->jobs.end() || it->second->done) fail(MBL_EINVAL, "unknown or finished ticket");
+    Job* j = it->second.get();
+    auto q = std::find(srv->pending.begin(), srv->pending.end(), j);
+    if (q == srv->pending.end()) {
+      j->cancel = 1;  // running: the solve stops at its next check
+      return MBL_OK;
+    }
+    srv->pending.erase(q);
+    j->r.status = MBL_ECANCELLED;
+    j->r.latency = std::chrono::duration<double>(clk::now() - j->submitted).count();
+    j->done = true;
+    ++srv->completed;
+  }
+  srv->cv_done.notify_all();
+  srv->cv_work.notify_all();
+  return MBL_OK;
+}
+
 mbl_status server_stats(Server* srv, mbl_server_stats* st) {
   std::lock_guard<std::mutex> lk(srv->mu);
   st->submitted = srv->submitted;
@@ -356,7 +384,11 @@ void server_destroy(Server* srv) {
   }
   srv->cv_work.notify_all();
   for (auto& t : srv->workers) t.join();
-  if (srv->copy) (void)hipStreamDestroy(srv->copy);
+  srv->jobs.clear();  // results never waited for: their vectors free on `copy`
+  if (srv->copy) {
+    (void)hipStreamSynchronize(srv->copy);
+    (void)hipStreamDestroy(srv->copy);
+  }
   delete srv;
 }
 

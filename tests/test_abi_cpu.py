@@ -52,7 +52,22 @@ def test_validation_without_device(lib):
                                 None) == _lib.MBL_EINVAL
     assert lib.mbl_small_eigh(0, None, 1, None, None, 1, None) == _lib.MBL_EINVAL
     assert lib.mbl_batch_solve(-1, None, None, 1) == _lib.MBL_EINVAL
-    assert lib.mbl_server_create(0, 0, C.byref(out)) == _lib.MBL_EINVAL
+    assert lib.mbl_server_create(0, 0, 0, C.byref(out)) == _lib.MBL_EINVAL  # no slots
+    assert lib.mbl_server_cancel(None, 1) == _lib.MBL_EINVAL
+
+
+def test_allocator_callbacks_install_and_restore(lib):
+    """Installing and removing callbacks needs no device; both callbacks or
+    neither."""
+    from paper_2012_00217_amd import _lib, api
+    api.use_allocator(lambda n, s: 0, lambda p, s: None)
+    assert api._allocator is not None
+    api.use_allocator(None)
+    assert api._allocator is None
+    assert lib.mbl_set_allocator(_lib.AllocFn(lambda n, s, c: 0), _lib.FreeFn(), None) == \
+        _lib.MBL_EINVAL
+    api.use_torch_allocator()
+    assert api._allocator is not None
 
 
 def test_footprint_model():

@@ -49,7 +49,7 @@ def test_batch_reports_per_problem_errors():
 
 def test_server_results_equal_alone_and_in_the_mix():
     probs = _problems()
-    with api.Server(concurrency=3) as srv:
+    with api.Server(max_slots=3) as srv:
         tickets = [srv.submit(dict(d, want_vectors=True)) for d in probs]
         outs = []
         for t, d in zip(tickets, probs):
@@ -69,7 +69,7 @@ def test_server_results_equal_alone_and_in_the_mix():
 def test_server_admission_refuses_oversized_request():
     d = _problems()[0]
     budget = api.footprint_bytes(14, 16, "f64") + 1000
-    with api.Server(concurrency=2, hbm_budget=budget) as srv:
+    with api.Server(max_slots=2, hbm_budget=budget) as srv:
         t_small = srv.submit(d)  # L=12 fits
         with pytest.raises(api.MblError) as e:
             srv.submit(dict(d, L=16, h=workloads.disorder(16, 4.0, 1)))
@@ -82,7 +82,7 @@ def test_server_admission_refuses_oversized_request():
 
 def test_server_wait_timeout_returns_none():
     d = dict(_problems()[4], L=18, h=workloads.disorder(18, 4.0, 3), nev=16, block=32)
-    with api.Server(concurrency=1) as srv:
+    with api.Server(max_slots=1) as srv:
         t = srv.submit(d)
         assert srv.wait(t, timeout=0.0) is None
         r = srv.wait(t)
@@ -99,7 +99,7 @@ def test_heterogeneous_mix_equals_alone_and_oracle():
         probs.append({"L": L, "Sz": Sz, "J": J, "Delta": Delta, "h": workloads.disorder(L, 5.0, 200 + j),
                       "eps": 0.3 + 0.1 * j, "nev": 6, "block": 12, "tol": 1e-10, "precision": prec,
                       "seed": 11})
-    with api.Server(concurrency=4) as srv:
+    with api.Server(max_slots=4) as srv:
         tickets = [srv.submit(d) for d in probs]
         mixed = [srv.wait(t) for t in tickets]
     alone = api.batch_solve(probs, concurrency=1)
