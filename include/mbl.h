@@ -148,6 +148,22 @@ mbl_status mbl_gram(mbl_precision prec, int64_t n, const void* A, int64_t lda,
                     int p, const void* B, int64_t ldb, int q, double* C_dev,
                     int64_t ldc, hipStream_t stream);
 
+/* mbl_gram without any device allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, kernels, reduction order and
+ * results (bitwise) as mbl_gram.  The per-split partial sums go to a fixed
+ * array of MBL_GRAM_SCRATCH_BYTES in device memory, one per GPU, held from
+ * the library's first use of this call on that GPU until the process ends.
+ * Shapes whose partials do not fit (p, q beyond about 2048 columns; the
+ * library computes splits x p x q x 8 bytes) return MBL_EINVAL.  All calls on
+ * one GPU share the array: calls that may overlap on that GPU (two streams,
+ * two threads) race and must be serialised by the caller.  Async. */
+#define MBL_GRAM_SCRATCH_BYTES ((size_t)64 << 20)
+mbl_status mbl_gram_noalloc(mbl_precision prec, int64_t n, const void* A,
+                            int64_t lda, int p, const void* B, int64_t ldb,
+                            int q, double* C_dev, int64_t ldc,
+                            hipStream_t stream);
+
 /* Y (n x q) = A (n x p) C (p x q, FP64 device, row-major ldc) in element type
  * prec.  Y must not overlap A.  Async. */
 mbl_status mbl_block_combine(mbl_precision prec, int64_t n, const void* A,

@@ -84,6 +84,7 @@ PROTOTYPES = {
     "mbl_fold_apply": (cint, [vp, dbl, cint, vp, i64, vp, i64, vp, i64, cint, vp]),
     "mbl_pcg": (cint, [vp, dbl, cint, vp, i64, vp, i64, cint, cint, vp]),
     "mbl_gram": (cint, [cint, i64, vp, i64, cint, vp, i64, cint, vp, i64, vp]),
+    "mbl_gram_noalloc": (cint, [cint, i64, vp, i64, cint, vp, i64, cint, vp, i64, vp]),
     "mbl_block_combine": (cint, [cint, i64, vp, i64, cint, vp, i64, vp, i64, cint, vp]),
     "mbl_small_eigh": (cint, [cint, vp, i64, vp, vp, i64, vp]),
     "mbl_spectrum_bounds": (cint, [vp, dbl, dptr, dptr, vp]),

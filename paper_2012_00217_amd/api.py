@@ -295,6 +295,23 @@ def gram(A, B, stream=None):
     return Cm
 
 
+def gram_noalloc(A, B, out, stream=None):
+    """A^T B into the caller's FP64 (p, q) device matrix `out`, with no device
+    allocation: the library's fixed per-GPU scratch holds the partial sums
+    (same kernels and bits as gram()).  Calls that overlap on one GPU race."""
+    pa, lda = _block(A, "A")
+    pb, ldb = _block(B, "B")
+    if A.dtype != B.dtype or A.shape[0] != B.shape[0]:
+        raise ValueError("A and B must share dtype and row count")
+    if (out.dtype != torch.float64 or out.device != A.device or out.dim() != 2
+            or tuple(out.shape) != (A.shape[1], B.shape[1]) or out.stride(1) != 1):
+        raise ValueError("out must be an FP64 (p, q) row-major device matrix beside A")
+    _lib.check(_lib.load().mbl_gram_noalloc(_prec(A), A.shape[0], pa, lda, A.shape[1], pb, ldb,
+                                            B.shape[1], C.c_void_p(out.data_ptr()),
+                                            out.stride(0), _stream(stream)))
+    return out
+
+
 def block_combine(A, Cm, stream=None):
     """A @ Cm with Cm an FP64 (p, q) device matrix; result in A's dtype."""
     pa, lda = _block(A, "A")

@@ -336,6 +336,31 @@ mbl_status mbl_gram(mbl_precision prec, int64_t n, const void* A, int64_t lda, i
   });
 }
 
+mbl_status mbl_gram_noalloc(mbl_precision prec, int64_t n, const void* A, int64_t lda, int p,
+                            const void* B, int64_t ldb, int q, double* C_dev, int64_t ldc,
+                            hipStream_t s) {
+  return guard([&] {
+    require(block_prec(prec), "precision must be MBL_F64 or MBL_F32");
+    require(n >= 0 && p >= 1 && q >= 1, "bad sizes");
+    check_block(A, lda, p, "A is NULL");
+    check_block(B, ldb, q, "B is NULL");
+    require(C_dev != nullptr && ldc >= q, "bad C");
+    const GramPlan g = gram_plan(n, p, q, A == B && lda == ldb);
+    if (g.part_bytes > kGramScratchBytes)
+      fail(MBL_EINVAL, "mbl_gram_noalloc: this shape needs " + std::to_string(g.part_bytes) +
+                           " bytes of partial sums, above the fixed " +
+                           std::to_string(kGramScratchBytes) + " (use mbl_gram)");
+    double* part = gram_scratch();
+    if (prec == MBL_F64)
+      launch_gram_part<double>(g, n, static_cast<const double*>(A), lda, p,
+                               static_cast<const double*>(B), ldb, q, C_dev, ldc, part, s);
+    else
+      launch_gram_part<float>(g, n, static_cast<const float*>(A), lda, p,
+                              static_cast<const float*>(B), ldb, q, C_dev, ldc, part, s);
+    return MBL_OK;
+  });
+}
+
 mbl_status mbl_block_combine(mbl_precision prec, int64_t n, const void* A, int64_t lda, int p,
                              const double* C_dev, int64_t ldc, void* Y, int64_t ldy, int q, hipStream_t s) {
   return guard([&] {

@@ -10,6 +10,8 @@
 //    C (rounded to the block type), register-tiled through LDS.
 //  * Precision conversion and the counter-based random starting block.
 #include <algorithm>
+#include <mutex>
+#include <string>
 
 #include "common.h"
 
@@ -297,35 +299,80 @@ inline unsigned g1(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 }  // namespace
 
+GramPlan gram_plan(int64_t n, int p, int q, bool same_operand) {
+  GramPlan g;
+  // A^T A: only the upper tiles (the Rayleigh-Ritz and Cholesky-QR Grams)
+  g.sym = (same_operand && p == q) ? 1 : 0;
+  const int tq = (q + 63) / 64;
+  g.tiles = g.sym ? tq * (tq + 1) / 2 : ((p + 63) / 64) * tq;
+  if (n == 0) {  // one split of zero rows: the kernel writes zero partials
+    g.splits = 1;
+    g.rows = kSlab;
+  } else {
+    int64_t splits = std::max<int64_t>(1, 1024 / g.tiles);
+    splits = std::min<int64_t>(splits, std::max<int64_t>(1, (n + 255) / 256));
+    int64_t rows = (n + splits - 1) / splits;
+    rows = ((rows + kSlab - 1) / kSlab) * kSlab;
+    g.rows = rows;
+    g.splits = std::max<int64_t>(1, (n + rows - 1) / rows);
+  }
+  g.part_bytes = (size_t)g.splits * p * q * sizeof(double);
+  return g;
+}
+
+template <class T>
+void launch_gram_part(const GramPlan& g, int64_t n, const T* A, int64_t lda, int p, const T* B,
+                      int64_t ldb, int q, double* C, int64_t ldc, double* part, hipStream_t s) {
+  if (p == 0 || q == 0) return;
+  PhaseTick tick(PhaseClock::GRAM, s);
+  const uintptr_t align = reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B) |
+                          (uintptr_t)(lda * (int64_t)sizeof(T)) |
+                          (uintptr_t)(ldb * (int64_t)sizeof(T));
+  const int vec = (align % 16) == 0;
+  hipLaunchKernelGGL(k_gram<T>, dim3(g.tiles, (unsigned)g.splits), dim3(256), 0, s, n, A, lda, p,
+                     B, ldb, q, g.sym, vec, g.rows, part);
+  MBL_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_gram_fold, dim3((unsigned)(((int64_t)p * q + 3) / 4)), dim3(256), 0, s,
+                     part, (int)g.splits, p, q, g.sym, C, ldc);
+  MBL_CHECK_LAUNCH();
+}
+
 template <class T>
 void launch_gram(int64_t n, const T* A, int64_t lda, int p, const T* B, int64_t ldb, int q,
                  double* C, int64_t ldc, hipStream_t s) {
   if (p == 0 || q == 0) return;
-  PhaseTick tick(PhaseClock::GRAM, s);
-  // A^T A: only the upper tiles (the Rayleigh-Ritz and Cholesky-QR Grams)
-  const int sym = (A == B && lda == ldb && p == q) ? 1 : 0;
-  const int tq = (q + 63) / 64;
-  const int tiles = sym ? tq * (tq + 1) / 2 : ((p + 63) / 64) * tq;
-  int64_t splits = std::max<int64_t>(1, 1024 / tiles);
-  splits = std::min<int64_t>(splits, std::max<int64_t>(1, (n + 255) / 256));
-  int64_t rows = (n + splits - 1) / splits;
-  rows = ((rows + kSlab - 1) / kSlab) * kSlab;
-  splits = std::max<int64_t>(1, (n + rows - 1) / rows);
-  DevBuf part((size_t)splits * p * q * sizeof(double), s);
-  if (n > 0) {
-    const uintptr_t align = reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B) |
-                            (uintptr_t)(lda * (int64_t)sizeof(T)) |
-                            (uintptr_t)(ldb * (int64_t)sizeof(T));
-    const int vec = (align % 16) == 0;
-    hipLaunchKernelGGL(k_gram<T>, dim3(tiles, (unsigned)splits), dim3(256), 0, s, n, A, lda, p, B,
-                       ldb, q, sym, vec, rows, part.as<double>());
-    MBL_CHECK_LAUNCH();
-  } else {
-    MBL_HIP(hipMemsetAsync(part.get(), 0, part.bytes(), s));
+  const GramPlan g = gram_plan(n, p, q, A == B && lda == ldb);
+  DevBuf part(g.part_bytes, s);
+  launch_gram_part<T>(g, n, A, lda, p, B, ldb, q, C, ldc, part.as<double>(), s);
+}
+
+// ---- Gram partials in a fixed device array -------------------------------
+// For callers that cannot allocate device memory (graph capture, tight
+// loops): the per-split partial sums live in this file-scope array instead
+// of a DevBuf.  Every k_gram launch writes each partial the fold reads, so
+// nothing needs clearing between calls.  One copy per device; host code uses
+// only the address hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) double scratch[kGramScratchBytes / sizeof(double)];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch[kMaxDevices] = {};
+}  // namespace
+
+double* gram_scratch() {
+  int dev = 0;
+  MBL_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) fail(MBL_EDEVICE, "device ordinal out of range for the Gram scratch");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch[dev] == nullptr) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || ptr == nullptr)
+      fail(MBL_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch[dev] = static_cast<double*>(ptr);
   }
-  hipLaunchKernelGGL(k_gram_fold, dim3((unsigned)(((int64_t)p * q + 3) / 4)), dim3(256), 0, s,
-                     part.as<double>(), (int)splits, p, q, sym, C, ldc);
-  MBL_CHECK_LAUNCH();
+  return g_scratch[dev];
 }
 
 template <class T>
@@ -364,6 +411,12 @@ template void launch_gram<double>(int64_t, const double*, int64_t, int, const do
                                   int, double*, int64_t, hipStream_t);
 template void launch_gram<float>(int64_t, const float*, int64_t, int, const float*, int64_t, int,
                                  double*, int64_t, hipStream_t);
+template void launch_gram_part<double>(const GramPlan&, int64_t, const double*, int64_t, int,
+                                       const double*, int64_t, int, double*, int64_t, double*,
+                                       hipStream_t);
+template void launch_gram_part<float>(const GramPlan&, int64_t, const float*, int64_t, int,
+                                      const float*, int64_t, int, double*, int64_t, double*,
+                                      hipStream_t);
 template void launch_combine<double>(int64_t, const double*, int64_t, int, const double*, int64_t,
                                      double*, int64_t, int, double, hipStream_t);
 template void launch_combine<float>(int64_t, const float*, int64_t, int, const double*, int64_t,

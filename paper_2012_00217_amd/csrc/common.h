@@ -293,6 +293,23 @@ template <class T>
 void launch_gram(int64_t n, const T* A, int64_t lda, int p, const T* B, int64_t ldb, int q,
                  double* C, int64_t ldc, hipStream_t s);
 
+// Launch plan of the Gram: tiles x splits workgroups, each split's FP64
+// partial p x q tile in `part` (part_bytes).  The plan depends only on
+// (n, p, q, same operand), so every caller sums in the same order.
+struct GramPlan {
+  int sym = 0, tiles = 0;
+  int64_t splits = 0, rows = 0;
+  size_t part_bytes = 0;
+};
+GramPlan gram_plan(int64_t n, int p, int q, bool same_operand);
+template <class T>
+void launch_gram_part(const GramPlan& g, int64_t n, const T* A, int64_t lda, int p, const T* B,
+                      int64_t ldb, int q, double* C, int64_t ldc, double* part, hipStream_t s);
+// Device address of the fixed Gram scratch (kGramScratchBytes) on the current
+// device; looked up once per device.
+constexpr size_t kGramScratchBytes = MBL_GRAM_SCRATCH_BYTES;
+double* gram_scratch();
+
 // Y = A C (+ beta Y), C FP64 (p x q).
 template <class T>
 void launch_combine(int64_t n, const T* A, int64_t lda, int p, const double* C, int64_t ldc, T* Y,
