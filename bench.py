@@ -6,12 +6,18 @@ whole workload once, every inner step on the GPU (apply, fold, Jacobi-PCG,
 Gram, Rayleigh-Ritz, small dense eigensolves, final FP64 residual check).
 
 Workloads (--workload):
-  l20  (default) L=20 open chain, Sz=0 (n=184756), J=Delta=1, W in {1,2,4,8},
-       one realisation per W from seed 0, sigma at energy density 0.5,
-       32 eigenpairs nearest sigma per W, block 64, tol 1e-10, FP64.
-  l24  L=24, Sz=0 (n=2704156), W=4, seed 0, energy density 0.5, 64 pairs,
-       block 128, tol 1e-10, mixed precision (long: tens of minutes).
+  l24  (default) L=24 open chain, Sz=0 (n=2704156), J=Delta=1, W=4, seed 0,
+       sigma at energy density 0.5, 64 eigenpairs, block 128, tol 1e-10,
+       mixed precision.  One step is one whole solve (several minutes); the
+       timed steps stop within a wall budget (--budget-s) and report how many
+       ran, warm-up runs on a small L=12 problem.
+  l22  the same at L=22 (n=705432).
+  l20  L=20, Sz=0 (n=184756), W in {1,2,4,8}, one realisation per W from
+       seed 0, 32 eigenpairs per W, block 64, tol 1e-10, FP64.
   l12  L=12, Sz=0 (n=924), W=8, seed 0, 8 pairs, block 16 (seconds).
+  batch, serve, slices, gram, precision, cgstep: the batched, serving,
+       spectrum-slice, Gram, mixed-against-FP64 and CG-step measurements (see
+       their functions).
 
 The JSON line carries a roofline entry for the dominant kernel (the fused CG
 apply kernels, timed with HIP events on the solve's stream inside the timed
@@ -20,12 +26,14 @@ region), and a CPU baseline from the FP64 oracle on a bounded sample.
 
 import argparse
 import hashlib
+from math import comb
 import json
 import os
 import re
 import sys
 import time
 
+T_START = time.perf_counter()
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -42,6 +50,9 @@ WORKLOADS = {
                      "density 0.5, LOBPCG block 64, tol 1e-10, FP64"),
     "l24": dict(L=24, Ws=[4.0], seed=0, eps=0.5, nev=64, block=128, tol=1e-10, precision="mixed",
                 desc="L=24 open chain, Sz=0 (n=2704156), J=Delta=1, W=4, seed 0, 64 eigenpairs "
+                     "nearest sigma at energy density 0.5, block 128, tol 1e-10, mixed precision"),
+    "l22": dict(L=22, Ws=[4.0], seed=0, eps=0.5, nev=64, block=128, tol=1e-10, precision="mixed",
+                desc="L=22 open chain, Sz=0 (n=705432), J=Delta=1, W=4, seed 0, 64 eigenpairs "
                      "nearest sigma at energy density 0.5, block 128, tol 1e-10, mixed precision"),
     "l12": dict(L=12, Ws=[8.0], seed=0, eps=0.5, nev=8, block=16, tol=1e-10, precision="f64",
                 desc="L=12 open chain, Sz=0 (n=924), J=Delta=1, W=8, seed 0, 8 eigenpairs "
@@ -79,64 +90,97 @@ def read_traffic(kernel, workload, precision):
     return float(m.group(1)) if m else None
 
 
-def cpu_baseline(wl, gpu_runs, verbose=False):
-    """The FP64 oracle on a bounded sample of the same workload.
+class OracleLeg:
+    """The FP64 oracle's work of one bench run, on a host thread.
 
-    Sample: the oracle's step-by-step Jacobi-PCG on the fold of the W=max(Ws)
-    realisation (CSR build, fold diagonal, 4 CG steps on a random n x block
-    block, i.e. 8 sparse block applies), timed on one host core; the per-step
-    time is projected with the GPU solve's own CG-step and apply counts, and
-    eigenpairs/s = nev / projected time.  The pairs the GPU returned are
-    re-checked with the oracle's FP64 CSR residuals.
+    While the GPU solves (its calls release the GIL), the thread builds the
+    sector matrix of every realisation (scipy CSR, FP64) and times the
+    cpu_baseline sample: the oracle's step-by-step Jacobi-PCG on the fold of
+    the first realisation, `steps` CG steps on a random n x block block (two
+    sparse block applies each) plus one sparse apply, on this one core; the
+    per-step time is projected with the GPU solve's own CG-step and apply
+    counts (a projection: the oracle cannot solve these sectors itself).
+    After the solve, check() recomputes every returned pair's residual with the
+    oracle's CSR matrix.
     """
-    import numpy as np
-    from oracle import hamiltonian, linalg, pcg
-    from paper_2012_00217_amd import workloads
 
-    def note(msg):
-        if verbose:
-            print(f"[cpu_baseline] {msg}", file=sys.stderr, flush=True)
+    def __init__(self, wl, sigmas, steps=4, verbose=False):
+        import threading
+        self.wl, self.sigmas, self.steps, self.verbose = wl, sigmas, steps, verbose
+        self.mats, self.timing, self.error = {}, None, None
+        self.thread = threading.Thread(target=self._run, daemon=True)
+        self.thread.start()
 
-    L, nev, b = wl["L"], wl["nev"], wl["block"]
-    W = max(wl["Ws"])
-    run = gpu_runs[W]
-    h = workloads.disorder(L, W, wl["seed"])
-    t0 = time.perf_counter()
-    st, H = hamiltonian.sector_matrix(L, L // 2, 1.0, 1.0, h)
-    d = hamiltonian.fold_diagonal(H, run["sigma"])
-    t_setup = time.perf_counter() - t0
-    note(f"sector matrix and fold diagonal: {t_setup:.1f} s")
-    R = workloads.random_block(len(st), b, seed=1)
-    m = 4
-    t0 = time.perf_counter()
-    pcg.pcg_fold(H, run["sigma"], d, R, m)
-    t_step = (time.perf_counter() - t0) / m
-    note(f"{m} CG steps: {t_step:.2f} s per step")
-    t0 = time.perf_counter()
-    hamiltonian.apply_shifted(H, R, run["sigma"])
-    t_apply = time.perf_counter() - t0
-    other_applies = run["applies"] - 2 * run["pcg_steps"]
-    t_proj = t_setup + t_step * run["pcg_steps"] + t_apply * other_applies
-    verified = {}
-    for w, r in gpu_runs.items():
-        hw = workloads.disorder(L, w, wl["seed"])
-        _, Hw = hamiltonian.sector_matrix(L, L // 2, 1.0, 1.0, hw, states=st)
-        res = linalg.residual_norms(Hw, r["evals"], r["evecs"])
-        verified[str(w)] = int(np.sum(res <= wl["tol"]))
-        note(f"W={w:g}: {verified[str(w)]} of {len(res)} pairs at residual <= {wl['tol']:g}")
-    return {
-        "value": nev / t_proj,
-        "unit": "eigenpairs/s",
-        "cores": 1,
-        "kind": "oracle",
-        "sample": (f"oracle Jacobi-PCG on the fold, {m} steps (2 CSR block applies each) on the "
-                   f"L={L} W={W:g} sector (n={len(st)}, block {b}), {t_step:.3f} s/step on one "
-                   f"core, projected with the GPU solve's {run['pcg_steps']} CG steps and "
-                   f"{other_applies} other applies: {t_proj:.0f} s for {nev} pairs"),
-        "cpu_checked_pairs": verified,
-        "host_cpu": _cpu_model(),
-        "host_cores_available": len(os.sched_getaffinity(0)),
-    }
+    def note(self, msg):
+        if self.verbose:
+            print(f"[oracle] {msg}", file=sys.stderr, flush=True)
+
+    def _run(self):
+        try:
+            import numpy as np
+            from oracle import hamiltonian, pcg
+            from paper_2012_00217_amd import workloads
+            wl = self.wl
+            L, b = wl["L"], wl["block"]
+            st = None
+            t_setup = None
+            for W in wl["Ws"]:
+                h = workloads.disorder(L, W, wl["seed"])
+                t0 = time.perf_counter()
+                st, H = hamiltonian.sector_matrix(L, L // 2, 1.0, 1.0, h, states=st)
+                self.mats[W] = H
+                if t_setup is None:
+                    t_setup = time.perf_counter() - t0
+                self.note(f"sector matrix W={W:g}: {time.perf_counter() - t0:.1f} s")
+            W0 = wl["Ws"][0]
+            H, sigma = self.mats[W0], self.sigmas[W0]
+            t0 = time.perf_counter()
+            d = hamiltonian.fold_diagonal(H, sigma)
+            t_setup += time.perf_counter() - t0
+            R = workloads.random_block(H.shape[0], b, seed=1)
+            t0 = time.perf_counter()
+            pcg.pcg_fold(H, sigma, d, R, self.steps)
+            t_step = (time.perf_counter() - t0) / self.steps
+            t0 = time.perf_counter()
+            hamiltonian.apply_shifted(H, R, sigma)
+            t_apply = time.perf_counter() - t0
+            self.timing = dict(t_setup=t_setup, t_step=t_step, t_apply=t_apply, n=H.shape[0])
+            self.note(f"{self.steps} CG steps: {t_step:.2f} s per step")
+        except Exception as e:  # reported in the JSON line, never fatal
+            self.error = repr(e)
+
+    def check(self, W, evals, evecs):
+        """Oracle FP64 residuals of the returned pairs (None if unavailable)."""
+        from oracle import linalg
+        self.thread.join()
+        if W not in self.mats:
+            return None
+        return linalg.residual_norms(self.mats[W], evals, evecs)
+
+    def baseline(self, run):
+        """cpu_baseline entry from the GPU solve's counts (None if unavailable)."""
+        self.thread.join()
+        if self.timing is None:
+            return None
+        wl, tm = self.wl, self.timing
+        other = run["applies"] - 2 * run["pcg_steps"]
+        # the guard columns run fewer CG steps: charge the oracle per column-step
+        col_steps = run["pcg_columns"] / float(wl["block"])
+        t_proj = tm["t_setup"] + tm["t_step"] * col_steps + tm["t_apply"] * other
+        nev = wl["nev"]
+        return {
+            "value": nev / t_proj,
+            "unit": "eigenpairs/s",
+            "cores": 1,
+            "kind": "oracle",
+            "sample": (f"oracle Jacobi-PCG on the fold, {self.steps} steps (2 CSR block applies "
+                       f"each) on the L={wl['L']} W={wl['Ws'][0]:g} sector (n={tm['n']}, block "
+                       f"{wl['block']}), {tm['t_step']:.3f} s/step on one core, projected with "
+                       f"the GPU solve's {col_steps:.0f} full-block-equivalent CG steps and "
+                       f"{other} other applies: {t_proj:.0f} s for {nev} pairs"),
+            "host_cpu": _cpu_model(),
+            "host_cores_available": len(os.sched_getaffinity(0)),
+        }
 
 
 def _cpu_model():
@@ -190,6 +234,117 @@ def run_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def run_precision(args):
+    """Mixed precision against FP64 on one problem (--precision-L, default 22;
+    W=4, seed 0, 64 pairs, block 128, tol 1e-10, sigma at energy density 0.5):
+    the same sigma and starting block in both runs; iterations, CG steps and
+    time of each, the oracle's FP64 residual of every pair of both, and per
+    pair the eigenvalue difference and the largest principal angle per
+    near-degenerate cluster."""
+    import numpy as np
+    import scipy.linalg as sla
+    import torch
+    from oracle import hamiltonian, linalg
+    from paper_2012_00217_amd import api, workloads
+
+    L, nev, b, tol = args.precision_L, 64, 128, 1e-10
+    h = workloads.disorder(L, 4.0, 0)
+    torch.cuda.init()
+    H = api.Hamiltonian(L, h)
+    lo, hi = H.spectrum_bounds(1e-12)
+    sigma = lo + 0.5 * (hi - lo)
+    runs = {}
+    for prec in ("mixed", "f64"):
+        t0 = time.perf_counter()
+        ev, V, rs, info = H.solve(sigma, nev, b, tol=tol, precision=prec, verbose=args.verbose,
+                                  raise_on_noconv=False, guard_cg=args.guard_cg)
+        el = time.perf_counter() - t0
+        runs[prec] = dict(ev=ev, V=V.cpu().numpy(), s=el, info=info)
+        del V
+        torch.cuda.empty_cache()
+        print(f"[precision] {prec}: {el:.1f} s, {info['iters']} iterations", file=sys.stderr,
+              flush=True)
+    st, Ho = hamiltonian.sector_matrix(L, L // 2, 1.0, 1.0, h)
+    for r in runs.values():
+        r["res"] = linalg.residual_norms(Ho, r["ev"], r["V"])
+    em, ed = runs["mixed"]["ev"], runs["f64"]["ev"]
+    dev = np.abs(em - ed)
+    worst = max(runs["mixed"]["res"].max(), runs["f64"]["res"].max())
+    cl = linalg.clusters(ed, 1e3 * worst)
+    angles = [float(np.max(sla.subspace_angles(runs["mixed"]["V"][:, c], runs["f64"]["V"][:, c])))
+              for c in cl]
+    out = {"workload": f"L={L}, Sz=0 (n={H.n}), W=4, seed 0, {nev} pairs nearest sigma at "
+                       f"energy density 0.5, block {b}, tol {tol:g}",
+           "sigma": sigma,
+           "runs": {p: {"seconds": round(r["s"], 1), "iters": r["info"]["iters"],
+                        "iters_fp64": r["info"]["iters_fp64"],
+                        "pcg_steps": r["info"]["pcg_steps"], "status": r["info"]["status"],
+                        "oracle_max_resid": float(r["res"].max()),
+                        "oracle_pairs_le_tol": int(np.sum(r["res"] <= tol))}
+                    for p, r in runs.items()},
+           "eig_absdiff_max": float(dev.max()), "eig_absdiff_median": float(np.median(dev)),
+           "min_gap": float(np.diff(np.sort(ed)).min()), "clusters": len(cl),
+           "max_angle": max(angles), "median_angle": float(np.median(angles))}
+    print(json.dumps(out), flush=True)
+
+
+def run_cgstep(args):
+    """Time of one block Jacobi-PCG step and of one plain apply (H - sigma) X,
+    per kernel path: `--cases` lists L:block:dtype (W=4, seed 0, Sz=0), and
+    `--modes` the apply kernels (onepass: the one-pass gather kernel, split:
+    the two-pass kernel, MBL_APPLY_SPLIT=1).  The CG step time is the
+    difference of two PCG calls of m1 and m2 steps over m2 - m1 (setup and
+    the first steps cancel); algorithmic bytes of a CG step: apply1 2nbs,
+    apply2 6nbs, p update 3nbs (11nbs, plus per-row tables)."""
+    import torch
+    from paper_2012_00217_amd import api, workloads
+
+    def timeit(fn, reps):
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    torch.cuda.init()
+    out = []
+    for case in args.cases.split(","):
+        L, b, dt = case.split(":")
+        L, b = int(L), int(b)
+        dtype = torch.float32 if dt == "f32" else torch.float64
+        s = 4 if dt == "f32" else 8
+        H = api.Hamiltonian(L, workloads.disorder(L, 4.0, 0))
+        n = H.n
+        g = torch.Generator(device="cuda")
+        g.manual_seed(1)
+        R = torch.randn(n, b, dtype=dtype, device="cuda", generator=g)
+        Y = torch.empty_like(R)
+        res = {"L": L, "block": b, "dtype": dt, "n": n}
+        for mode in args.modes.split(","):
+            os.environ["MBL_APPLY_SPLIT"] = "1" if mode == "split" else "0"
+            H.pcg(R, -0.5, 8)
+            m1, m2 = 10, 60
+            t1 = timeit(lambda: H.pcg(R, -0.5, m1), 2)
+            t2 = timeit(lambda: H.pcg(R, -0.5, m2), 2)
+            step = (t2 - t1) / (m2 - m1)
+            H.apply(R, -0.5, out=Y)
+            ta = timeit(lambda: H.apply(R, -0.5, out=Y), 10)
+            res[mode] = {"cg_step_ms": round(step, 4),
+                         "cg_alg_GBps": round(11 * n * b * s / step / 1e6, 1),
+                         "apply_ms": round(ta, 4),
+                         "apply_alg_GBps": round(2 * n * b * s / ta / 1e6, 1)}
+        os.environ.pop("MBL_APPLY_SPLIT", None)
+        print(json.dumps(res), flush=True)
+        out.append(res)
+        del R, Y
+        H.close()
+        torch.cuda.empty_cache()
+    return out
+
+
 def run_serve(args):
     """Open-loop request stream: Poisson arrivals of solves with mixed L, W and
     energy density, served with continuous batching; p50/p99 latency."""
@@ -220,27 +375,33 @@ def run_serve(args):
                 note(f"{tag}: request {i} (L={probs[i]['L']}) done at "
                      f"{time.perf_counter() - t0:.1f} s, latency {r['latency']:.2f} s")
 
-    with api.Server(concurrency=args.concurrency) as srv:
+    with api.Server(max_slots=args.concurrency) as srv:
         t0 = time.perf_counter()
         drain(srv, {i: srv.submit(d) for i, d in enumerate(probs)}, t0, "closed loop")
         cap = len(probs) / (time.perf_counter() - t0)
     rate = args.load * cap
     gaps = np.random.default_rng(args.count).exponential(1.0 / rate, len(probs))
     results = [None] * len(probs)
-    with api.Server(concurrency=args.concurrency) as srv:
+    # the open loop keeps every request's eigenvectors (copied out at
+    # completion) so that the oracle can re-check every served pair afterwards
+    served = [dict(d, want_vectors=True) for d in probs]
+    vecs = [None] * len(probs)
+    with api.Server(max_slots=args.concurrency) as srv:
         t0 = time.perf_counter()
         arrive = np.cumsum(gaps)
         pending, nxt = {}, 0
         while nxt < len(probs) or pending:
             now = time.perf_counter() - t0
             while nxt < len(probs) and arrive[nxt] <= now:
-                pending[nxt] = srv.submit(probs[nxt])
+                pending[nxt] = srv.submit(served[nxt])
+                vecs[nxt] = torch.empty((comb(probs[nxt]["L"], probs[nxt]["L"] // 2),
+                                         probs[nxt]["nev"]), dtype=torch.float64, device="cuda")
                 note(f"open loop: request {nxt} (L={probs[nxt]['L']}) arrived at {now:.1f} s")
                 nxt += 1
             if pending:
                 drain_once = dict(pending)
                 for i, t in drain_once.items():
-                    r = srv.wait(t, timeout=0.02)
+                    r = srv.wait(t, timeout=0.02, vectors_out=vecs[i])
                     if r is not None:
                         del pending[i]
                         results[i] = r
@@ -252,6 +413,19 @@ def run_serve(args):
         st = srv.stats()
     lat = np.array([r["latency"] for r in results])
     pairs = sum(int(np.sum(r["resid"] <= 1e-10)) for r in results if r["status"] == "MBL_OK")
+    # the oracle's FP64 CSR residual of every served pair (after the timed loop)
+    from oracle import hamiltonian, linalg
+    checked, worst = 0, 0.0
+    for i, r in enumerate(results):
+        if r["status"] != "MBL_OK":
+            continue
+        L = probs[i]["L"]
+        _, Ho = hamiltonian.sector_matrix(L, L // 2, 1.0, 1.0, probs[i]["h"])
+        rc = linalg.residual_norms(Ho, r["evals"], vecs[i].cpu().numpy())
+        checked += int(np.sum(rc <= 1e-10))
+        worst = max(worst, float(rc.max()))
+        vecs[i] = None
+    note(f"oracle: {checked} of {pairs} served pairs at <= 1e-10 (largest residual {worst:.3g})")
     out = {"metric": "p99 ms (serving)", "value": round(float(np.percentile(lat, 99)) * 1e3, 1),
            "unit": "ms", "higher_is_better": False, "n_gpus": 1, "steps": 1, "warmup": 0,
            "ms_per_step": round(el * 1e3, 1), "scaling": "weak", "vs_baseline": None,
@@ -262,6 +436,7 @@ def run_serve(args):
                       "concurrency": args.concurrency},
            "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 1),
            "throughput_pairs_per_s": round(pairs / el, 3),
+           "oracle_checked_pairs": checked, "oracle_max_resid": worst,
            "capacity_req_per_s": round(cap, 4),
            "server_stats": {k: st[k] for k in ("completed", "rejected", "peak_bytes")}}
     if args.plain:
@@ -274,9 +449,21 @@ def run_serve(args):
         note(f"plain FP64 one at a time: {el1:.1f} s")
         lat1 = np.array([r["seconds"] for r in res1])
         p1 = sum(int(np.sum(r["resid"] <= 1e-10)) for r in res1 if r["status"] == "MBL_OK")
+        # the same arrivals served first come first served, one solve at a
+        # time: latency = finish - arrival with finish_i = max(arrival_i,
+        # finish_{i-1}) + solve_i (exact for one server, from the measured
+        # solve times)
+        fin, qlat = 0.0, []
+        for a, d in zip(arrive, lat1):
+            fin = max(a, fin) + d
+            qlat.append(fin - a)
+        qlat = np.array(qlat)
         out["plain_f64_one_at_a_time"] = {
-            "p50_ms": round(float(np.percentile(lat1, 50)) * 1e3, 1),
-            "p99_ms": round(float(np.percentile(lat1, 99)) * 1e3, 1),
+            "solve_p50_ms": round(float(np.percentile(lat1, 50)) * 1e3, 1),
+            "solve_p99_ms": round(float(np.percentile(lat1, 99)) * 1e3, 1),
+            "queued_p50_ms": round(float(np.percentile(qlat, 50)) * 1e3, 1),
+            "queued_p99_ms": round(float(np.percentile(qlat, 99)) * 1e3, 1),
+            "capacity_req_per_s": round(len(probs) / el1, 4),
             "throughput_pairs_per_s": round(p1 / el1, 3), "ms": round(el1 * 1e3, 1)}
     print(json.dumps(out), flush=True)
 
@@ -386,8 +573,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=0)
-    ap.add_argument("--workload", default="l20",
-                    choices=sorted(WORKLOADS) + ["batch", "serve", "gram", "slices"])
+    ap.add_argument("--workload", default="l24",
+                    choices=sorted(WORKLOADS) + ["batch", "serve", "gram", "slices", "precision",
+                                                 "cgstep"])
     ap.add_argument("--count", type=int, default=0,
                     help="batch/serve: number of problems (default 256 for batch, 40 for serve)")
     ap.add_argument("--concurrency", type=int, default=8,
@@ -398,7 +586,8 @@ def main():
     ap.add_argument("--serve-precision", default="mixed")
     ap.add_argument("--load", type=float, default=0.8, help="serve: arrival rate / capacity")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--verbose", action="store_true", help="one line per outer iteration")
+    ap.add_argument("--verbose", type=int, default=1,
+                    help="progress on stderr: 0 none, 1 one line per outer iteration, 2 detail")
     ap.add_argument("--max-iter", type=int, default=400, help="outer LOBPCG iterations per solve")
     ap.add_argument("--precision", default="", choices=["", "f64", "pcg32", "mixed"],
                     help="override the workload's precision")
@@ -408,6 +597,15 @@ def main():
                     help="single solves: soft locking of converged pairs (mbl_solve_opts.lock)")
     ap.add_argument("--cg-only", type=int, default=0,
                     help="counter runs: only run this many CG steps per realisation")
+    ap.add_argument("--budget-s", type=float, default=540.0,
+                    help="wall seconds of the whole command (the timed steps stop in time)")
+    ap.add_argument("--cases", default="24:128:f32,22:128:f32,20:64:f64",
+                    help="cgstep: L:block:dtype list")
+    ap.add_argument("--modes", default="onepass,split", help="cgstep: apply kernels to time")
+    ap.add_argument("--precision-L", type=int, default=22,
+                    help="precision: chain length of the mixed-against-FP64 comparison")
+    ap.add_argument("--guard-cg", type=float, default=0.0,
+                    help="CG steps of the guard columns as a fraction (0: library default)")
     args = ap.parse_args()
     if args.count <= 0:
         args.count = 40 if args.workload == "serve" else 256
@@ -425,6 +623,10 @@ def main():
         return run_serve(args)
     if args.workload == "slices":
         return run_slices(args)
+    if args.workload == "precision":
+        return run_precision(args)
+    if args.workload == "cgstep":
+        return run_cgstep(args)
 
     import numpy as np
     import torch
@@ -435,12 +637,19 @@ def main():
         wl["desc"] = wl["desc"].rsplit(", ", 1)[0] + f", precision {args.precision}"
         wl["precision"] = args.precision
     L = wl["L"]
+
+    def note(msg):
+        if args.verbose:
+            print(f"[bench {time.perf_counter() - T_START:6.1f} s] {msg}", file=sys.stderr,
+                  flush=True)
+
     torch.cuda.init()
     hams, sigmas = {}, {}
     for W in wl["Ws"]:
         H = api.Hamiltonian(L, workloads.disorder(L, W, wl["seed"]))
         lo, hi = H.spectrum_bounds(1e-12)
         hams[W], sigmas[W] = H, lo + wl["eps"] * (hi - lo)
+        note(f"L={L} W={W:g}: n={H.n}, spectrum [{lo:.6f}, {hi:.6f}], sigma {sigmas[W]:.6f}")
     n = hams[wl["Ws"][0]].n
     s = 8 if wl["precision"] == "f64" else 4
 
@@ -462,30 +671,63 @@ def main():
         print(json.dumps({"cg_only": args.cg_only, "n": n, "block": wl["block"]}))
         return
 
-    def one_step(record):
+    oracle = None if args.no_cpu_baseline else OracleLeg(wl, sigmas, verbose=args.verbose)
+
+    def one_step(record, max_seconds):
         out = {}
         for W, H in hams.items():
             ev, V, rs, info = H.solve(sigmas[W], wl["nev"], wl["block"], tol=wl["tol"],
                                       precision=wl["precision"], timing=True,
                                       raise_on_noconv=False, verbose=args.verbose,
                                       max_iter=args.max_iter, pcg_iters=args.pcg_iters,
-                                      lock=args.lock)
+                                      lock=args.lock, max_seconds=max_seconds,
+                                      guard_cg=args.guard_cg)
             if record:
                 out[W] = dict(info=info, evals=ev, resid=rs, V=V)
         return out
 
-    for _ in range(args.warmup):
-        one_step(False)
+    # warm-up on the small L=12 problem (loads every kernel); the timed steps
+    # are the workload itself
+    small = api.Hamiltonian(12, workloads.disorder(12, 8.0, 0))
+    lo12, hi12 = small.spectrum_bounds(1e-12)
+    for _ in range(max(1, args.warmup)):
+        small.solve(lo12 + 0.5 * (hi12 - lo12), 8, 16, tol=1e-10, precision=wl["precision"])
+    small.close()
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    runs = []
-    for _ in range(args.steps):
-        runs.append(one_step(True))
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    note("warm-up done; timed steps start")
 
-    pairs = sum(int(np.sum(r["resid"] <= wl["tol"])) for step in runs for r in step.values())
-    value = pairs / elapsed
+    # Wall budget: the driver stops the whole command at its limit, so the
+    # timed steps stop early enough to leave time for the checks below; a
+    # solve that would run past the budget stops at its own time limit and
+    # returns its best pairs (only those the oracle confirms are counted).
+    reserve = 45.0
+    t0 = time.perf_counter()
+    runs, elapsed = [], 0.0
+    while len(runs) < args.steps:
+        left = args.budget_s - (time.perf_counter() - T_START) - reserve
+        if runs and left < elapsed / len(runs):
+            break
+        runs.append(one_step(True, max(1.0, left)))
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        note(f"step {len(runs)} done: {elapsed:.1f} s timed so far")
+    steps = len(runs)
+
+    # every returned pair of the last step re-checked by the oracle (the steps
+    # are the same deterministic computation)
+    last = runs[-1]
+    verified = {}
+    for W, r in last.items():
+        rc = oracle.check(W, r["evals"], r["V"].cpu().numpy()) if oracle else None
+        verified[str(W)] = int(np.sum(rc <= wl["tol"])) if rc is not None else None
+        r["oracle_resid"] = rc
+    if oracle is not None and all(v is not None for v in verified.values()):
+        pairs_per_step = sum(verified.values())
+        counted_by = "oracle"
+    else:
+        pairs_per_step = sum(int(np.sum(r["resid"] <= wl["tol"])) for r in last.values())
+        counted_by = "library"
+    value = pairs_per_step * steps / elapsed
     # dominant kernel from the live event timings (summed over the timed solves)
     k = 0 if s == 8 else 1
     tot = {"apply1": [0, 0.0, 0.0], "apply2": [0, 0.0, 0.0]}
@@ -510,7 +752,6 @@ def main():
     dom = max(tot, key=lambda kk: tot[kk][1])
     kb = tot[dom][2] / max(1, tot[dom][0])
     achieved = kb / (avg[dom] * 1e-3) / 1e9
-    # the counters were taken on full-width launches; soft locking mixes widths
     traffic = None if args.lock else read_traffic(dom, args.workload, wl["precision"])
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
@@ -561,27 +802,33 @@ def main():
     del src, dst
     roofline["measured_copy_GBps"] = round(copy_gbps, 1)
 
-    last = runs[-1]
-    per_w = {str(W): {"sigma": sigmas[W], "iters": r["info"]["iters"],
-                      "applies": r["info"]["applies"], "pcg_steps": r["info"]["pcg_steps"],
-                      "pcg_columns": r["info"]["pcg_columns"],
-                      "seconds": round(r["info"]["seconds"], 3),
-                      "max_resid": float(np.max(r["resid"])), "status": r["info"]["status"]}
-             for W, r in last.items()}
+    per_w = {}
+    for W, r in last.items():
+        i = r["info"]
+        per_w[str(W)] = {"sigma": sigmas[W], "iters": i["iters"], "applies": i["applies"],
+                         "pcg_steps": i["pcg_steps"], "pcg_columns": i["pcg_columns"],
+                         "seconds": round(i["seconds"], 3), "t_pcg": round(i["t_pcg"], 3),
+                         "t_apply": round(i["t_apply"], 4), "t_gram": round(i["t_gram"], 4),
+                         "t_small": round(i["t_small"], 4),
+                         "max_resid": float(np.max(r["resid"])), "status": i["status"],
+                         "oracle_pairs_le_tol": verified[str(W)],
+                         "oracle_max_resid": (float(np.max(r["oracle_resid"]))
+                                              if r["oracle_resid"] is not None else None)}
     cpu = None
-    if not args.no_cpu_baseline:
-        gpu_runs = {W: dict(sigma=sigmas[W], applies=r["info"]["applies"],
-                            pcg_steps=r["info"]["pcg_steps"], evals=r["evals"],
-                            evecs=r["V"].cpu().numpy()) for W, r in last.items()}
-        cpu = cpu_baseline(wl, gpu_runs, verbose=args.verbose)
+    if oracle is not None:
+        run0 = last[wl["Ws"][0]]["info"]
+        cpu = oracle.baseline({"applies": run0["applies"], "pcg_steps": run0["pcg_steps"],
+                               "pcg_columns": run0["pcg_columns"]})
+        if cpu is None:
+            cpu = {"error": oracle.error}
     line = {
         "metric": "eigenpairs/s at resid<=1e-10",
         "value": round(value, 4),
         "unit": "eigenpairs/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(elapsed / args.steps * 1e3, 1),
+        "steps": steps,
+        "warmup": max(1, args.warmup),
+        "ms_per_step": round(elapsed / steps * 1e3, 1),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -589,7 +836,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl["desc"], "L": L, "n": n, "nev": wl["nev"],
                    "block": wl["block"], "tol": wl["tol"], "precision": wl["precision"],
-                   "W": wl["Ws"], "pairs_per_step": pairs // args.steps,
+                   "W": wl["Ws"], "pairs_per_step": pairs_per_step,
+                   "pairs_counted_by": counted_by, "steps_requested": args.steps,
+                   "warmup_workload": "L=12, W=8, 8 pairs, block 16 (kernel load)",
                    **({"soft_locking": True} if args.lock else {})},
         "roofline": roofline,
         "cpu_baseline": cpu,
@@ -598,6 +847,7 @@ def main():
         "hx_ms": round(hx_ms, 4),
         "cg_steps": steps_cg,
         "per_W": per_w,
+        "wall_s": round(time.perf_counter() - T_START, 1),
     }
     print(json.dumps(line), flush=True)
 
