@@ -69,10 +69,11 @@ def apply_src_hash():
     return h.hexdigest()[:16]
 
 
-def read_traffic(kernel, workload, precision):
+def read_traffic(kernel, workload, precision, width=None):
     """HBM bytes per launch from the committed counter summary, or None if the
     summary is missing, covers another workload or precision, or was taken
-    from a different kernel source."""
+    from a different kernel source.  `width`: the launch's column count (the
+    summary holds one value per width the counters were taken at)."""
     path = COUNTERS.format(workload)
     if not os.path.exists(path):
         return None
@@ -86,7 +87,8 @@ def read_traffic(kernel, workload, precision):
     m = re.search(r"apply_src_sha256_16:\s*([0-9a-f]+)", txt)
     if not m or m.group(1) != apply_src_hash():
         return None
-    m = re.search(rf"{kernel}_hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    key = f"{kernel}_hbm_bytes_per_launch" + (f"_w{width}" if width else "")
+    m = re.search(rf"{key}:\s*([0-9.eE+]+)", txt)
     return float(m.group(1)) if m else None
 
 
@@ -597,6 +599,9 @@ def main():
                     help="single solves: soft locking of converged pairs (mbl_solve_opts.lock)")
     ap.add_argument("--cg-only", type=int, default=0,
                     help="counter runs: only run this many CG steps per realisation")
+    ap.add_argument("--cg-widths", default="",
+                    help="counter runs: block widths of the CG calls (default: the block, "
+                         "then nev when the solve narrows the CG to the wanted columns)")
     ap.add_argument("--budget-s", type=float, default=540.0,
                     help="wall seconds of the whole command (the timed steps stop in time)")
     ap.add_argument("--cases", default="24:128:f32,22:128:f32,20:64:f64",
@@ -663,12 +668,19 @@ def main():
             torch.mul(src, 1.5, out=dst)
         torch.cuda.synchronize()
         del src, dst
+        # the CG widths of the solve: every column, then the wanted ones alone
+        # when the guard columns stop early (n >= 500000, see the library)
+        widths = ([int(x) for x in args.cg_widths.split(",")] if args.cg_widths else
+                  [wl["block"]] + ([wl["nev"]] if n >= 500000 and wl["nev"] < wl["block"]
+                                   else []))
         for W, H in hams.items():
-            R = torch.randn(n, wl["block"], dtype=torch.float64 if s == 8 else torch.float32,
-                            device="cuda")
-            H.pcg(R, sigmas[W], args.cg_only)
+            for w in widths:
+                R = torch.randn(n, w, dtype=torch.float64 if s == 8 else torch.float32,
+                                device="cuda")
+                H.pcg(R, sigmas[W], args.cg_only)
+                del R
         torch.cuda.synchronize()
-        print(json.dumps({"cg_only": args.cg_only, "n": n, "block": wl["block"]}))
+        print(json.dumps({"cg_only": args.cg_only, "n": n, "widths": widths}))
         return
 
     oracle = None if args.no_cpu_baseline else OracleLeg(wl, sigmas, verbose=args.verbose)
@@ -728,21 +740,25 @@ def main():
         pairs_per_step = sum(int(np.sum(r["resid"] <= wl["tol"])) for r in last.values())
         counted_by = "library"
     value = pairs_per_step * steps / elapsed
-    # dominant kernel from the live event timings (summed over the timed solves)
+    # dominant kernel from the live event timings: every CG launch of the
+    # timed solves, its device time estimated per inner CG call from the
+    # event-timed sample of that call (the library's *_all fields)
     k = 0 if s == 8 else 1
-    tot = {"apply1": [0, 0.0, 0.0], "apply2": [0, 0.0, 0.0]}
-    steps_cg = 0
+    tot = {"apply1": [0, 0.0, 0.0, 0, 0.0], "apply2": [0, 0.0, 0.0, 0, 0.0]}
+    steps_cg, cols_cg = 0, 0
     for step in runs:
         for r in step.values():
             i = r["info"]
             for kk in ("apply1", "apply2"):
-                tot[kk][0] += i[f"cg_{kk}_launches"][k]
-                tot[kk][1] += i[f"cg_{kk}_ms"][k]
-                tot[kk][2] += i[f"cg_{kk}_bytes"][k]
+                tot[kk][0] += i["cg_launches_all"][k]
+                tot[kk][1] += i[f"cg_{kk}_ms_all"][k]
+                tot[kk][2] += i[f"cg_{kk}_bytes_all"][k]
+                tot[kk][3] += i[f"cg_{kk}_launches"][k]
+                tot[kk][4] += i[f"cg_{kk}_ms"][k]
             steps_cg += i["pcg_steps"]
-    avg = {kk: (v[1] / v[0] if v[0] else float("nan")) for kk, v in tot.items()}
+            cols_cg += i["pcg_columns"]
     # Algorithmic bytes per launch over w columns of s-byte scalars (summed by
-    # the library over the timed launches):
+    # the library over the launches):
     #   apply1  T = (H - sigma) p, |T|^2: read p, write T, state word and
     #           diagonal per row                     -> 2 n w s + 12 n
     #   apply2  q = (H - sigma) T, x += alpha p, r -= alpha q, r.M^-1 r: read
@@ -750,16 +766,40 @@ def main():
     #                                                -> 6 n w s + (12 + s) n
     # dominant: the larger total time (both kernels run once per CG step)
     dom = max(tot, key=lambda kk: tot[kk][1])
-    kb = tot[dom][2] / max(1, tot[dom][0])
-    achieved = kb / (avg[dom] * 1e-3) / 1e9
-    traffic = None if args.lock else read_traffic(dom, args.workload, wl["precision"])
+    nl, ms_all, bytes_all, nsample, ms_sample = tot[dom]
+    kb = bytes_all / max(1, nl)
+    avg_ms = ms_all / max(1, nl)
+    achieved = kb / (avg_ms * 1e-3) / 1e9
+    # CG launches per width: every column (b) until the guard columns stop,
+    # then the nev wanted ones: x + y = launches, b x + nev y = column-steps
+    b_, v_ = wl["block"], wl["nev"]
+    widths = {}
+    if args.lock:
+        widths = None
+    elif nl == steps_cg:
+        y = (b_ * steps_cg - cols_cg) / float(b_ - v_) if b_ > v_ else 0.0
+        if abs(y - round(y)) < 1e-6 and 0 <= y <= steps_cg:
+            widths = {b_: steps_cg - int(round(y))}
+            if y > 0:
+                widths[v_] = int(round(y))
+    traffic = None
+    if widths:
+        per_w = {w: read_traffic(dom, args.workload, wl["precision"], w) for w in widths}
+        if len(widths) == 1 and per_w[b_] is None:
+            per_w[b_] = read_traffic(dom, args.workload, wl["precision"])
+        if all(v is not None for v in per_w.values()):
+            traffic = sum(per_w[w] * c for w, c in widths.items()) / sum(widths.values())
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                "traffic": traffic,
                 "kernel": f"k_apply fused CG {dom} ({'FP64' if s == 8 else 'FP32'}, "
-                          f"{wl['block']}-column block"
-                          f"{', narrower once pairs lock' if args.lock else ''})",
-                "algorithmic_bytes_per_launch": kb, "avg_launch_us": round(avg[dom] * 1e3, 2),
-                "timed_launches": tot[dom][0]}
+                          + (", ".join(f"{c} launches over {w} columns"
+                                       for w, c in widths.items()) if widths else
+                             f"{wl['block']}-column block, narrower once pairs lock"
+                             if args.lock else f"{wl['block']}-column block") + ")",
+                "algorithmic_bytes_per_launch": kb, "avg_launch_us": round(avg_ms * 1e3, 2),
+                "launches": nl, "timed_launches": nsample,
+                "timed_avg_launch_us": round(ms_sample / max(1, nsample) * 1e3, 2)}
 
     # H X bandwidth of the plain apply (after the timed region)
     H0 = hams[wl["Ws"][0]]

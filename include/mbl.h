@@ -249,6 +249,14 @@ typedef struct {
      the small dense kernels (eigensolver, Cholesky, small products)        */
   double t_apply, t_gram, t_small;
   int cg_split;          /* the timed CG steps ran the two-pass kernels      */
+  /* opts.timing: every CG step of the solve (the timed ones are the first up
+     to 64 of each inner CG call, of each column chunk): launches of each CG
+     kernel, their algorithmic bytes, and their device milliseconds estimated
+     per inner CG call as the timed launches' mean times its steps (the other
+     steps replay the same launches from a captured graph).  [0]=FP64 [1]=FP32 */
+  int64_t cg_launches_all[2];
+  double cg_apply1_ms_all[2], cg_apply2_ms_all[2];
+  double cg_apply1_bytes_all[2], cg_apply2_bytes_all[2];
 } mbl_solve_info;
 
 mbl_status mbl_solve_opts_default(mbl_solve_opts* opts);

@@ -35,7 +35,10 @@ class SolveInfo(C.Structure):
                 ("cg_apply1_ms", C.c_double * 2), ("cg_apply2_ms", C.c_double * 2),
                 ("cg_apply1_bytes", C.c_double * 2), ("cg_apply2_bytes", C.c_double * 2),
                 ("pcg_columns", C.c_int64), ("t_apply", C.c_double), ("t_gram", C.c_double),
-                ("t_small", C.c_double), ("cg_split", C.c_int)]
+                ("t_small", C.c_double), ("cg_split", C.c_int),
+                ("cg_launches_all", C.c_int64 * 2),
+                ("cg_apply1_ms_all", C.c_double * 2), ("cg_apply2_ms_all", C.c_double * 2),
+                ("cg_apply1_bytes_all", C.c_double * 2), ("cg_apply2_bytes_all", C.c_double * 2)]
 
 
 class Problem(C.Structure):

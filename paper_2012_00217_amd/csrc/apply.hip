@@ -828,22 +828,31 @@ void run_pcg_split(const Ham& H, double sigma, const T* jac, const T* Rc, int64_
     const int nwp2 = split_cg_apply<T>(H, sigma, 1, sg, s);
     fin(nwp2, FB{}, s);
   };
-  replay_steps(step, it, m, s, stop);
+  const int run = replay_steps(step, it, m, s, stop);
   if (ntimed > 0) {
     MBL_HIP(hipStreamSynchronize(s));
+    double sa = 0.0, sc = 0.0;
     for (int k = 0; k < ntimed; ++k) {
       float ta = 0.f, tc = 0.f;
       MBL_HIP(hipEventElapsedTime(&ta, tm->ev[4 * k + 0], tm->ev[4 * k + 1]));
       MBL_HIP(hipEventElapsedTime(&tc, tm->ev[4 * k + 2], tm->ev[4 * k + 3]));
-      tm->ms[0] += ta;
-      tm->ms[1] += tc;
+      sa += ta;
+      sc += tc;
     }
-    tm->launches[0] += ntimed;
-    tm->launches[1] += ntimed;
     // algorithmic bytes: apply1 (p-update fused) reads r, p and writes p, T;
     // apply2 reads T, p, x, r and writes x, r
-    tm->bytes[0] += (double)ntimed * 4.0 * n * w * sizeof(T);
-    tm->bytes[1] += (double)ntimed * 6.0 * n * w * sizeof(T);
+    const double b1 = 4.0 * n * w * sizeof(T), b2 = 6.0 * n * w * sizeof(T);
+    tm->ms[0] += sa;
+    tm->ms[1] += sc;
+    tm->launches[0] += ntimed;
+    tm->launches[1] += ntimed;
+    tm->bytes[0] += ntimed * b1;
+    tm->bytes[1] += ntimed * b2;
+    tm->launches_all += run;
+    tm->ms_all[0] += sa / ntimed * run;
+    tm->ms_all[1] += sc / ntimed * run;
+    tm->bytes_all[0] += run * b1;
+    tm->bytes_all[1] += run * b2;
     tm->split = true;
   }
 }
@@ -938,20 +947,30 @@ void run_pcg(const Ham& H, double sigma, const T* jac, const T* R, int64_t ldr, 
       }
       // The remaining steps replay one captured step: every CG coefficient
       // lives on the device, so the five launches are identical each step.
-      replay_steps(step, it, to, s, stop);
+      const int run = replay_steps(step, it, to, s, stop) - from;
       if (ntimed > 0) {
         MBL_HIP(hipStreamSynchronize(s));
+        double sa = 0.0, sc = 0.0;
         for (int k = 0; k < ntimed; ++k) {
           float ta = 0.f, tc = 0.f;
           MBL_HIP(hipEventElapsedTime(&ta, tm->ev[4 * k + 0], tm->ev[4 * k + 1]));
           MBL_HIP(hipEventElapsedTime(&tc, tm->ev[4 * k + 2], tm->ev[4 * k + 3]));
-          tm->ms[0] += ta;
-          tm->ms[1] += tc;
+          sa += ta;
+          sc += tc;
         }
+        const double b1 = 2.0 * n * ch.w * sizeof(T) + 12.0 * n;
+        const double b2 = 6.0 * n * ch.w * sizeof(T) + (12.0 + sizeof(T)) * n;
+        tm->ms[0] += sa;
+        tm->ms[1] += sc;
         tm->launches[0] += ntimed;
         tm->launches[1] += ntimed;
-        tm->bytes[0] += (double)ntimed * (2.0 * n * ch.w * sizeof(T) + 12.0 * n);
-        tm->bytes[1] += (double)ntimed * (6.0 * n * ch.w * sizeof(T) + (12.0 + sizeof(T)) * n);
+        tm->bytes[0] += ntimed * b1;
+        tm->bytes[1] += ntimed * b2;
+        tm->launches_all += run;
+        tm->ms_all[0] += sa / ntimed * run;
+        tm->ms_all[1] += sc / ntimed * run;
+        tm->bytes_all[0] += run * b1;
+        tm->bytes_all[1] += run * b2;
       }
     };
     for (const Chunk& ch : plan_chunks<T>(w, aligned, sc)) {
@@ -985,7 +1004,7 @@ void run_pcg(const Ham& H, double sigma, const T* jac, const T* R, int64_t ldr, 
           for (const Chunk& sub : plan_chunks<T>(keep - lo, aligned, sc)) {
             Chunk c2 = sub;
             c2.col0 += ch.col0;
-            cg_steps(c2, m, m_keep, false);
+            cg_steps(c2, m, m_keep, true);
           }
         }
       }

@@ -227,6 +227,12 @@ struct PcgTiming {
   int64_t launches[2] = {0, 0};
   double ms[2] = {0, 0};
   double bytes[2] = {0, 0};  // algorithmic bytes of the timed launches
+  // Every CG step run (the timed ones included): launches, algorithmic
+  // bytes, and device time estimated per CG call as its timed sample's mean
+  // times the steps that call ran (the untimed steps replay the same launches).
+  int64_t launches_all = 0;
+  double ms_all[2] = {0, 0};
+  double bytes_all[2] = {0, 0};
   bool split = false;        // the timed steps ran the two-pass kernels
   void init();
   ~PcgTiming();

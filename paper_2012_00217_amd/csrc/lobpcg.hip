@@ -801,6 +801,11 @@ mbl_status solve_interior(const Ham& H, double sigma, int nev, int b, double tol
       info->cg_apply1_bytes[k] = st.tm[k].bytes[0];
       info->cg_apply2_bytes[k] = st.tm[k].bytes[1];
       if (st.tm[k].split) info->cg_split = 1;
+      info->cg_launches_all[k] = st.tm[k].launches_all;
+      info->cg_apply1_ms_all[k] = st.tm[k].ms_all[0];
+      info->cg_apply2_ms_all[k] = st.tm[k].ms_all[1];
+      info->cg_apply1_bytes_all[k] = st.tm[k].bytes_all[0];
+      info->cg_apply2_bytes_all[k] = st.tm[k].bytes_all[1];
     }
     info->t_apply = 1e-3 * clock.ms[PhaseClock::APPLY];
     info->t_gram = 1e-3 * clock.ms[PhaseClock::GRAM];

@@ -143,6 +143,15 @@ def test_phase_timers():
     ev, V, rs, info = H.solve(sigma, 8, 16, tol=1e-10, timing=True)
     assert info["t_apply"] > 0 and info["t_gram"] > 0 and info["t_small"] > 0
     assert info["t_pcg"] > 0 and info["cg_apply1_launches"][0] > 0
+    # every CG step is counted once per kernel and column chunk; the timed
+    # launches are a sample of them
+    steps, nl = info["pcg_steps"], info["cg_launches_all"][0]
+    assert nl % steps == 0 and nl >= info["cg_apply1_launches"][0]
+    nch = nl // steps
+    assert info["cg_apply2_ms_all"][0] >= info["cg_apply2_ms"][0] > 0
+    n = H.n
+    assert info["cg_apply1_bytes_all"][0] == pytest.approx(steps * (2 * n * 16 * 8 + 12 * n * nch))
+    assert info["cg_apply2_bytes_all"][0] == pytest.approx(steps * (6 * n * 16 * 8 + 20 * n * nch))
     ev, V, rs, info = H.solve(sigma, 8, 16, tol=1e-10)
     assert info["t_apply"] == 0 and info["t_gram"] == 0
 
