@@ -343,7 +343,11 @@ mbl_status mbl_footprint_bytes(int L, double Sz, int block, int precision, size_
  * (status, sigma, counts, timings; evals/resid/evecs into caller buffers).
  * Returns MBL_OK if every problem converged, else the first problem's error.
  * With the environment variable MBL_VERBOSE=1, batch and server solves print
- * one line per outer iteration to stderr. */
+ * one line per outer iteration to stderr.  MBL_BATCH_FUSE=1 runs the inner CG
+ * calls of concurrent solves that share a launch plan as one launch per
+ * kernel (problem j's workgroups are its own grid, so results keep their
+ * bits); MBL_FUSE_WAIT_MS (default 0.5) is how long the first call of a group
+ * waits for the others, and MBL_FUSE_STATS=1 prints the groups formed. */
 mbl_status mbl_batch_solve(int count, const mbl_problem* problems, mbl_result* results,
                            int concurrency);
 

@@ -38,14 +38,17 @@ KNOBS = ("MBL_APPLY_CHUNK_BYTES", "MBL_APPLY_LANE_BYTES", "MBL_APPLY_XCD_GROUP",
 DEFAULT = (512, 64, 0, 256)
 
 # (L, block columns, element type): the shapes the solver's workloads run the
-# CG at -- single solves at L = 12, 20, 24, 28, the batched L = 14-18
-# realisations, and the FP32 CG of mixed-precision serving at L = 16-26.
+# CG at -- single solves at L = 12, 20, 22, 24, 28 (at L >= 22 also on the 64
+# wanted columns alone), the batched L = 14-18 realisations, and the FP32 CG
+# of mixed-precision serving at L = 16-26.
 SHAPES = [
     (12, 16, torch.float64), (14, 32, torch.float64), (16, 32, torch.float64),
     (18, 32, torch.float64), (20, 64, torch.float64), (22, 64, torch.float64),
     (24, 128, torch.float32), (24, 128, torch.float64), (28, 32, torch.float64),
     (16, 32, torch.float32), (18, 32, torch.float32), (20, 32, torch.float32),
     (22, 32, torch.float32), (24, 32, torch.float32), (26, 32, torch.float32),
+    # the wanted columns alone, once the guard columns of a large solve stop
+    (22, 64, torch.float32), (24, 64, torch.float32),
 ]
 
 
@@ -141,12 +144,32 @@ def write_table(results, path=TABLE, device_name=""):
         f.write("\n".join(lines) + "\n")
 
 
+def read_table(path=TABLE):
+    """Entries of an existing schedule table (the results format of tune_shape)."""
+    import re
+    out = []
+    pat = re.compile(r"\{(\d+), (\d+), (\d+), (\d+), \{(\d+), (\d+), (\d+), (\d+)\}\},\s*"
+                     r"// b=(\d+): ([0-9.]+) ms \(([0-9.]+) ms\)")
+    if not os.path.exists(path):
+        return out
+    for line in open(path):
+        m = pat.search(line)
+        if m and int(m.group(1)) > 0:
+            v = [int(x) for x in m.groups()[:9]]
+            out.append({"L": v[0], "n": v[1], "row_bytes": v[2], "elem": v[3],
+                        "sched": tuple(v[4:8]), "b": v[8], "ms": float(m.group(10)),
+                        "default_ms": float(m.group(11))})
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--write", action="store_true", help="rewrite the schedule table")
     ap.add_argument("--out", default=TABLE, help="table path for --write (default: csrc/apply_schedules.inc)")
     ap.add_argument("--shapes", default="", help="comma list of L:b:f32|f64 (default: built-in)")
     ap.add_argument("--json", default="", help="also dump the results to this file")
+    ap.add_argument("--merge", action="store_true",
+                    help="with --write: keep the table's entries for shapes not tuned now")
     a = ap.parse_args(argv)
     if not torch.cuda.is_available():
         sys.exit("autotune needs a GPU")
@@ -165,6 +188,11 @@ def main(argv=None):
     if a.json:
         with open(a.json, "w") as f:
             json.dump(results, f, indent=1)
+    if a.write and a.merge:
+        key = lambda r: (r["L"], r["row_bytes"], r["elem"])
+        fresh = {key(r) for r in results}
+        results = [r for r in read_table(a.out) if key(r) not in fresh] + results
+        results.sort(key=lambda r: (r["elem"], r["row_bytes"], r["L"]))
     if a.write:
         props = torch.cuda.get_device_properties(0)
         arch = getattr(props, "gcnArchName", "").split(":")[0]

@@ -26,8 +26,13 @@
 // reads contiguously) and folded by a separate kernel in workgroup order, so
 // every dot product is bitwise reproducible.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <cstdlib>
+#include <exception>
+#include <map>
+#include <mutex>
 
 #include "common.h"
 
@@ -156,7 +161,7 @@ constexpr int kThreads = 64 * kWaves;
 
 template <class T, int VE, int NV>
 __device__ inline void block_reduce_store(double (&red)[NV * VE], int log2G, int w,
-                                          double* __restrict__ part) {
+                                          double* __restrict__ part, int bid, int nwg) {
   extern __shared__ double sred[];  // [kWaves][w]
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int G = 1 << log2G;
@@ -174,9 +179,17 @@ __device__ inline void block_reduce_store(double (&red)[NV * VE], int log2G, int
     double s = sred[c];
 #pragma unroll
     for (int wv = 1; wv < kWaves; ++wv) s += sred[wv * w + c];
-    part[(int64_t)c * gridDim.x + blockIdx.x] = s;  // [column][workgroup]
+    part[(int64_t)c * nwg + bid] = s;  // [column][workgroup]
   }
 }
+
+// MBL_APPLY_ALPHA_LDS=1 (default): the fused CG update reads its step lengths
+// from LDS instead of holding them in registers, which brings the FP32
+// 128-column CG kernel from 177 to 165 registers (3 waves per SIMD instead of
+// 2; about 2% faster per CG step at L = 22 and 24).
+#ifndef MBL_APPLY_ALPHA_LDS
+#define MBL_APPLY_ALPHA_LDS 1
+#endif
 
 #ifndef MBL_APPLY_BB_BYTES
 #define MBL_APPLY_BB_BYTES 256
@@ -191,7 +204,7 @@ constexpr int kNoFlip = -2147483647 - 1;  // offset-table entry of an inactive b
 // lanes of a row read four offsets at a time (one LDS load) and gather the
 // target rows' column chunks.
 template <class T, int VE, int NV, int EPI>
-__global__ __launch_bounds__(kThreads) void k_apply(ApplyArgs<T> a) {
+__device__ __forceinline__ void apply_body(const ApplyArgs<T>& a, const int bid, const int nwg) {
   using P = Pack<T, VE>;
   constexpr int BB0 = MBL_APPLY_BB_BYTES / (NV * VE * (int)sizeof(T));
   constexpr int BB = BB0 <= 1 ? 1 : (BB0 >= 4 ? 4 : 2);  // bonds per batch of loads
@@ -214,6 +227,15 @@ __global__ __launch_bounds__(kThreads) void k_apply(ApplyArgs<T> a) {
   double red[NV * VE];
 #pragma unroll
   for (int k = 0; k < NV * VE; ++k) red[k] = 0.0;
+#if MBL_APPLY_ALPHA_LDS
+  // the CG step lengths of the chunk's columns in LDS (after the offset
+  // tables), read per row instead of held in registers
+  T* salpha = reinterpret_cast<T*>(reinterpret_cast<int*>(sdyn + red_doubles) + kWaves * RW * 32);
+  if constexpr (EPI == EPI_PCG) {
+    for (int c = threadIdx.x; c < a.w; c += kThreads) salpha[c] = (T)a.coef[a.col0 + c].alpha;
+    __syncthreads();
+  }
+#else
   T alpha[NV * VE];
   if constexpr (EPI == EPI_PCG) {
 #pragma unroll
@@ -221,11 +243,12 @@ __global__ __launch_bounds__(kThreads) void k_apply(ApplyArgs<T> a) {
 #pragma unroll
       for (int e = 0; e < VE; ++e) alpha[q * VE + e] = (T)a.coef[cbase + q * G * VE + e].alpha;
   }
+#endif
   const T hj = (T)a.halfJ;
 
-  const int xcd = blockIdx.x & 7;
-  const int nslots = gridDim.x >> 3;
-  for (int64_t u = blockIdx.x >> 3;; u += nslots) {
+  const int xcd = bid & 7;
+  const int nslots = nwg >> 3;
+  for (int64_t u = bid >> 3;; u += nslots) {
     bool done;
     const int64_t tile = sched_tile(a.ts, u, xcd, &done);
     if (done) break;
@@ -322,9 +345,16 @@ __global__ __launch_bounds__(kThreads) void k_apply(ApplyArgs<T> a) {
           P pv = load_once<T, VE>(pr + q * G * VE);
           P xv = load_once<T, VE>(xr + q * G * VE);
           P rv = load_once<T, VE>(rr + q * G * VE);
+#if MBL_APPLY_ALPHA_LDS
+          const P av = *reinterpret_cast<const P*>(salpha + (cbase - a.col0) + q * G * VE);
+#endif
 #pragma unroll
           for (int e = 0; e < VE; ++e) {
+#if MBL_APPLY_ALPHA_LDS
+            const T al = av.v[e];
+#else
             const T al = alpha[q * VE + e];
+#endif
             xv.v[e] = xv.v[e] + al * pv.v[e];
             rv.v[e] = rv.v[e] - al * acc[q * VE + e];
             red[q * VE + e] += (double)rv.v[e] * (double)(rv.v[e] * dinv);
@@ -339,7 +369,43 @@ __global__ __launch_bounds__(kThreads) void k_apply(ApplyArgs<T> a) {
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
-  if constexpr (EPI != EPI_PLAIN) block_reduce_store<T, VE, NV>(red, a.log2G, a.w, a.part);
+  if constexpr (EPI != EPI_PLAIN) block_reduce_store<T, VE, NV>(red, a.log2G, a.w, a.part, bid, nwg);
+}
+
+// MBL_APPLY_WAVES > 0 asks the compiler for at least that many waves per SIMD
+// (a register cap) on the apply kernels; 0 leaves the choice to it.
+#ifndef MBL_APPLY_WAVES
+#define MBL_APPLY_WAVES 0
+#endif
+#if MBL_APPLY_WAVES > 0
+#define MBL_APPLY_OCC __attribute__((amdgpu_waves_per_eu(MBL_APPLY_WAVES, 8)))
+#else
+#define MBL_APPLY_OCC
+#endif
+
+template <class T, int VE, int NV, int EPI>
+__global__ __launch_bounds__(kThreads) MBL_APPLY_OCC void k_apply(ApplyArgs<T> a) {
+  apply_body<T, VE, NV, EPI>(a, blockIdx.x, gridDim.x);
+}
+
+// Several problems in one launch (the fused CG of a batch): problem j owns
+// workgroups [wg0[j], wg0[j+1]); every wg0[j] is a multiple of 8, so each
+// problem's workgroups keep their XCDs, tiles and partial-sum slots of a launch
+// of their own, and the results are the same bits.
+constexpr int kMaxFuse = 8;
+
+template <class T>
+struct MultiApply {
+  int np;
+  int wg0[kMaxFuse + 1];
+  ApplyArgs<T> a[kMaxFuse];
+};
+
+template <class T, int VE, int NV, int EPI>
+__global__ __launch_bounds__(kThreads) MBL_APPLY_OCC void k_apply_multi(MultiApply<T> m) {
+  int j = 0;
+  while (j + 1 < m.np && (int)blockIdx.x >= m.wg0[j + 1]) ++j;
+  apply_body<T, VE, NV, EPI>(m.a[j], (int)blockIdx.x - m.wg0[j], m.wg0[j + 1] - m.wg0[j]);
 }
 
 // PCG element-wise kernels with the same lane layout as k_apply.
@@ -364,7 +430,7 @@ struct EltArgs {
 };
 
 template <class T, int VE, int NV, int MODE>
-__global__ __launch_bounds__(kThreads) void k_pcg_elt(EltArgs<T> a) {
+__device__ __forceinline__ void elt_body(const EltArgs<T>& a, const int bid, const int nwg) {
   using P = Pack<T, VE>;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int G = 1 << a.log2G;
@@ -387,9 +453,9 @@ __global__ __launch_bounds__(kThreads) void k_pcg_elt(EltArgs<T> a) {
         live[q * VE + e] = c.live != 0;
       }
   }
-  const int xcd = blockIdx.x & 7;
-  const int nslots = gridDim.x >> 3;
-  for (int64_t u = blockIdx.x >> 3;; u += nslots) {
+  const int xcd = bid & 7;
+  const int nslots = nwg >> 3;
+  for (int64_t u = bid >> 3;; u += nslots) {
     bool done;
     const int64_t tile = sched_tile(a.ts, u, xcd, &done);
     if (done) break;
@@ -422,7 +488,26 @@ __global__ __launch_bounds__(kThreads) void k_pcg_elt(EltArgs<T> a) {
       }
     }
   }
-  if constexpr (MODE == ELT_INIT) block_reduce_store<T, VE, NV>(red, a.log2G, a.w, a.part);
+  if constexpr (MODE == ELT_INIT) block_reduce_store<T, VE, NV>(red, a.log2G, a.w, a.part, bid, nwg);
+}
+
+template <class T, int VE, int NV, int MODE>
+__global__ __launch_bounds__(kThreads) void k_pcg_elt(EltArgs<T> a) {
+  elt_body<T, VE, NV, MODE>(a, blockIdx.x, gridDim.x);
+}
+
+template <class T>
+struct MultiElt {
+  int np;
+  int wg0[kMaxFuse + 1];
+  EltArgs<T> a[kMaxFuse];
+};
+
+template <class T, int VE, int NV, int MODE>
+__global__ __launch_bounds__(kThreads) void k_pcg_elt_multi(MultiElt<T> m) {
+  int j = 0;
+  while (j + 1 < m.np && (int)blockIdx.x >= m.wg0[j + 1]) ++j;
+  elt_body<T, VE, NV, MODE>(m.a[j], (int)blockIdx.x - m.wg0[j], m.wg0[j + 1] - m.wg0[j]);
 }
 
 // Fold the per-workgroup partials of one chunk (fixed order) and update the
@@ -432,13 +517,10 @@ __global__ __launch_bounds__(kThreads) void k_pcg_elt(EltArgs<T> a) {
 enum { FIN_INIT = 0, FIN_ALPHA = 1, FIN_BETA = 2 };
 
 template <int MODE>
-__global__ __launch_bounds__(kThreads) void k_pcg_finalize(const double* __restrict__ part,
-                                                           int nwg, int w, int col0,
-                                                           PcgCoef* __restrict__ coef) {
+__device__ __forceinline__ void fin_body(const double* __restrict__ part, int nwg, int col0,
+                                         PcgCoef* __restrict__ coef, int c) {
   __shared__ double swave[kWaves];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int c = blockIdx.x;
-  if (c >= w) return;  // uniform over the workgroup
   double s = 0.0;
   const double* pc = part + (int64_t)c * nwg;
   for (int g = threadIdx.x; g < nwg; g += kThreads) s += pc[g];
@@ -464,6 +546,32 @@ __global__ __launch_bounds__(kThreads) void k_pcg_finalize(const double* __restr
     k.beta = k.live ? s / k.rho : 0.0;
     if (k.live) k.rho = s;
   }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kThreads) void k_pcg_finalize(const double* __restrict__ part,
+                                                           int nwg, int w, int col0,
+                                                           PcgCoef* __restrict__ coef) {
+  if ((int)blockIdx.x >= w) return;  // uniform over the workgroup
+  fin_body<MODE>(part, nwg, col0, coef, blockIdx.x);
+}
+
+// One workgroup per (problem, column): problem j owns workgroups
+// [c0[j], c0[j+1]), one per column of its chunk.
+struct MultiFin {
+  int np;
+  int c0[kMaxFuse + 1];
+  const double* part[kMaxFuse];
+  int nwg[kMaxFuse];
+  int col0[kMaxFuse];
+  PcgCoef* coef[kMaxFuse];
+};
+
+template <int MODE>
+__global__ __launch_bounds__(kThreads) void k_pcg_finalize_multi(MultiFin m) {
+  int j = 0;
+  while (j + 1 < m.np && (int)blockIdx.x >= m.c0[j + 1]) ++j;
+  fin_body<MODE>(m.part[j], m.nwg[j], m.col0[j], m.coef[j], (int)blockIdx.x - m.c0[j]);
 }
 
 struct Chunk {
@@ -573,7 +681,8 @@ void dispatch_apply(const Chunk& ch, const Grid& g, ApplyArgs<T> a, hipStream_t 
   a.log2G = ch.log2G;
   a.ts = g.ts;
   const size_t shm = ((EPI == EPI_PLAIN) ? 0 : (size_t)kWaves * ch.w * sizeof(double)) +
-                     (size_t)kWaves * (64 >> ch.log2G) * 32 * sizeof(int);
+                     (size_t)kWaves * (64 >> ch.log2G) * 32 * sizeof(int) +
+                     ((MBL_APPLY_ALPHA_LDS && EPI == EPI_PCG) ? (size_t)ch.w * sizeof(T) : 0);
   constexpr int VV = 16 / sizeof(T);
 #define MBL_APPLY_CASE(VE_, NV_)                                                             \
   if (ch.VE == VE_ && ch.NV == NV_) {                                                       \
@@ -857,6 +966,267 @@ void run_pcg_split(const Ham& H, double sigma, const T* jac, const T* Rc, int64_
   }
 }
 
+// ---- fused block PCG of several problems --------------------------------
+//
+// Concurrent solves of a batch reach their inner CG at about the same time.
+// Instead of one launch per problem and kernel, a group of CG calls with the
+// same launch plan (element type, block width, step count, schedule and
+// alignment; the sector dimensions may differ) runs as one launch per kernel:
+// problem j owns a contiguous range of workgroups equal to its own grid, so
+// it sums its rows in the same order as alone and gets the same bits.  The
+// first caller of a group (the leader) waits a short time for peers, then
+// enqueues the whole group's CG on its stream and the other callers' streams
+// wait for it by events.
+
+template <class T>
+struct CgJob {
+  const Ham* H;
+  double sigma;
+  const T* jac;
+  const T* R;
+  int64_t ldr;
+  T* W;
+  int64_t ldw;
+  int b, m;
+  bool aligned;
+  Sched sc;
+  T *r, *p, *t;
+  double* part;
+  PcgCoef* coef;
+  hipStream_t s;
+};
+
+struct CgFuser {
+  struct Ticket {
+    std::vector<int64_t> key;
+    void* job;
+    hipEvent_t ready = nullptr, finished = nullptr;
+    bool done = false;
+    std::exception_ptr err;
+  };
+  std::mutex mu;
+  std::condition_variable cv;
+  std::map<std::vector<int64_t>, std::vector<Ticket*>> open;
+  int max_group;
+  std::chrono::microseconds wait;
+  int64_t groups = 0, jobs = 0;
+};
+
+// the argument blocks of the fused kernels stay within the 4 KB kernel
+// argument space
+static_assert(sizeof(MultiApply<double>) <= 4096 && sizeof(MultiElt<double>) <= 4096 &&
+                  sizeof(MultiFin) <= 4096,
+              "fused kernel arguments too large");
+
+template <class T>
+void run_pcg_fused(const std::vector<CgJob<T>*>& g, hipStream_t s) {
+  const int np = (int)g.size();
+  const CgJob<T>& j0 = *g[0];
+  const int b = j0.b, m = j0.m;
+  for (const Chunk& ch : plan_chunks<T>(b, j0.aligned, j0.sc)) {
+    std::vector<Grid> grid(np);
+    MultiApply<T> m1{}, m2{};
+    MultiElt<T> ei{}, eu{};
+    MultiFin fin{};
+    m1.np = m2.np = ei.np = eu.np = fin.np = np;
+    int wg = 0;
+    for (int k = 0; k < np; ++k) {
+      const CgJob<T>& J = *g[k];
+      const Grid gr = make_grid(J.H->n, ch.log2G, J.sc);
+      m1.wg0[k] = m2.wg0[k] = ei.wg0[k] = eu.wg0[k] = wg;
+      wg += (int)gr.nwg;
+      ApplyArgs<T> a1 = base_args<T>(*J.H, J.sigma);  // T = (H - sigma) p, |T|^2
+      a1.X = J.p;
+      a1.ldx = b;
+      a1.Y = J.t;
+      a1.ldy = b;
+      a1.part = J.part;
+      ApplyArgs<T> a2 = base_args<T>(*J.H, J.sigma);  // q = (H - sigma) T, CG update
+      a2.X = J.t;
+      a2.ldx = b;
+      a2.x = J.W;
+      a2.ldxv = J.ldw;
+      a2.r = J.r;
+      a2.ldr = b;
+      a2.p = J.p;
+      a2.ldp = b;
+      a2.jac = J.jac;
+      a2.coef = J.coef;
+      a2.part = J.part;
+      for (ApplyArgs<T>* a : {&a1, &a2}) {
+        a->col0 = ch.col0;
+        a->w = ch.w;
+        a->log2G = ch.log2G;
+        a->ts = gr.ts;
+      }
+      m1.a[k] = a1;
+      m2.a[k] = a2;
+      EltArgs<T> e{};
+      e.R = J.R;
+      e.ldR = J.ldr;
+      e.x = J.W;
+      e.ldxv = J.ldw;
+      e.r = J.r;
+      e.ldr = b;
+      e.p = J.p;
+      e.ldp = b;
+      e.jac = J.jac;
+      e.coef = J.coef;
+      e.part = J.part;
+      e.n = J.H->n;
+      e.col0 = ch.col0;
+      e.w = ch.w;
+      e.log2G = ch.log2G;
+      e.ts = gr.ts;
+      ei.a[k] = e;
+      eu.a[k] = e;
+      fin.c0[k] = k * ch.w;
+      fin.part[k] = J.part;
+      fin.nwg[k] = (int)gr.nwg;
+      fin.col0[k] = ch.col0;
+      fin.coef[k] = J.coef;
+    }
+    m1.wg0[np] = m2.wg0[np] = ei.wg0[np] = eu.wg0[np] = wg;
+    fin.c0[np] = np * ch.w;
+    const size_t red = (size_t)kWaves * ch.w * sizeof(double);
+    const size_t shm = red + (size_t)kWaves * (64 >> ch.log2G) * 32 * sizeof(int) +
+                       (MBL_APPLY_ALPHA_LDS ? (size_t)ch.w * sizeof(T) : 0);
+    constexpr int VV = 16 / sizeof(T);
+    auto launch_apply_multi = [&](const MultiApply<T>& ma, auto epi, hipStream_t st) {
+      constexpr int EPI = decltype(epi)::value;
+#define MBL_FUSE_CASE(VE_, NV_)                                                                 \
+  if (ch.VE == VE_ && ch.NV == NV_) {                                                           \
+    hipLaunchKernelGGL((k_apply_multi<T, VE_, NV_, EPI>), dim3(wg), dim3(kThreads), shm, st, ma); \
+    MBL_CHECK_LAUNCH();                                                                         \
+    return;                                                                                     \
+  }
+      MBL_FUSE_CASE(VV, 8)
+      MBL_FUSE_CASE(VV, 4)
+      MBL_FUSE_CASE(VV, 2)
+      MBL_FUSE_CASE(VV, 1)
+      MBL_FUSE_CASE(1, 4)
+      MBL_FUSE_CASE(1, 2)
+      MBL_FUSE_CASE(1, 1)
+#undef MBL_FUSE_CASE
+      fail(MBL_EINTERNAL, "fused pcg: no kernel for chunk shape");
+    };
+    auto launch_elt_multi = [&](const MultiElt<T>& me, auto mode, hipStream_t st) {
+      constexpr int MODE = decltype(mode)::value;
+      const size_t eshm = (MODE == ELT_INIT) ? red : 0;
+#define MBL_FUSE_ELT(VE_, NV_)                                                                     \
+  if (ch.VE == VE_ && ch.NV == NV_) {                                                              \
+    hipLaunchKernelGGL((k_pcg_elt_multi<T, VE_, NV_, MODE>), dim3(wg), dim3(kThreads), eshm, st, me); \
+    MBL_CHECK_LAUNCH();                                                                            \
+    return;                                                                                        \
+  }
+      MBL_FUSE_ELT(VV, 8)
+      MBL_FUSE_ELT(VV, 4)
+      MBL_FUSE_ELT(VV, 2)
+      MBL_FUSE_ELT(VV, 1)
+      MBL_FUSE_ELT(1, 4)
+      MBL_FUSE_ELT(1, 2)
+      MBL_FUSE_ELT(1, 1)
+#undef MBL_FUSE_ELT
+      fail(MBL_EINTERNAL, "fused pcg: no kernel for chunk shape");
+    };
+    auto launch_fin = [&](auto mode, hipStream_t st) {
+      constexpr int MODE = decltype(mode)::value;
+      hipLaunchKernelGGL(k_pcg_finalize_multi<MODE>, dim3(np * ch.w), dim3(kThreads), 0, st, fin);
+      MBL_CHECK_LAUNCH();
+    };
+    using E1 = std::integral_constant<int, EPI_NORM2>;
+    using E2 = std::integral_constant<int, EPI_PCG>;
+    using LI = std::integral_constant<int, ELT_INIT>;
+    using LU = std::integral_constant<int, ELT_PUPD>;
+    using FI = std::integral_constant<int, FIN_INIT>;
+    using FA = std::integral_constant<int, FIN_ALPHA>;
+    using FB = std::integral_constant<int, FIN_BETA>;
+    launch_elt_multi(ei, LI{}, s);
+    launch_fin(FI{}, s);
+    auto step = [&]() {
+      launch_apply_multi(m1, E1{}, s);
+      launch_fin(FA{}, s);
+      launch_apply_multi(m2, E2{}, s);
+      launch_fin(FB{}, s);
+      launch_elt_multi(eu, LU{}, s);
+    };
+    replay_steps(step, 0, m, s, nullptr);
+  }
+}
+
+CgFuser* cg_fuser_create(int max_group, double wait_ms) {
+  CgFuser* f = new CgFuser;
+  f->max_group = std::max(1, std::min(max_group, kMaxFuse));
+  f->wait = std::chrono::microseconds((int64_t)(1000.0 * std::max(0.0, wait_ms)));
+  return f;
+}
+
+void cg_fuser_destroy(CgFuser* f) { delete f; }
+
+void cg_fuser_stats(const CgFuser* f, int64_t* groups, int64_t* jobs) {
+  *groups = f->groups;
+  *jobs = f->jobs;
+}
+
+thread_local CgFuser* t_cg_fuser = nullptr;
+
+// One CG call through the fuser: returns after the call's work (its own or
+// its group's) is enqueued and `job.s` waits for it.
+template <class T>
+void fuse_pcg(CgFuser& f, CgJob<T>& job) {
+  std::vector<int64_t> key = {(int64_t)sizeof(T), job.b, job.m, job.aligned ? 1 : 0,
+                              job.sc.chunk_bytes, job.sc.lane_bytes, job.sc.grp, job.sc.slots};
+  CgFuser::Ticket tk;
+  tk.key = key;
+  tk.job = &job;
+  MBL_HIP(hipEventCreateWithFlags(&tk.ready, hipEventDisableTiming));
+  MBL_HIP(hipEventCreateWithFlags(&tk.finished, hipEventDisableTiming));
+  struct Events {
+    CgFuser::Ticket& t;
+    ~Events() {
+      (void)hipEventDestroy(t.ready);
+      (void)hipEventDestroy(t.finished);
+    }
+  } ev{tk};
+  MBL_HIP(hipEventRecord(tk.ready, job.s));  // R and the caller's buffers are ready
+  std::unique_lock<std::mutex> lk(f.mu);
+  auto& grp = f.open[key];
+  grp.push_back(&tk);
+  if (grp.size() > 1) {
+    if ((int)grp.size() >= f.max_group) f.cv.notify_all();
+    f.cv.wait(lk, [&] { return tk.done; });
+  } else {
+    // leader: gather peers, then run the group on this caller's stream
+    f.cv.wait_for(lk, f.wait, [&] { return (int)f.open[key].size() >= f.max_group; });
+    std::vector<CgFuser::Ticket*> members = std::move(f.open[key]);
+    f.open.erase(key);
+    ++f.groups;
+    f.jobs += (int64_t)members.size();
+    lk.unlock();
+    std::exception_ptr err;
+    try {
+      std::vector<CgJob<T>*> jobs;
+      for (CgFuser::Ticket* t : members) {
+        jobs.push_back(static_cast<CgJob<T>*>(t->job));
+        if (t != &tk) MBL_HIP(hipStreamWaitEvent(job.s, t->ready, 0));
+      }
+      run_pcg_fused<T>(jobs, job.s);
+      for (CgFuser::Ticket* t : members) MBL_HIP(hipEventRecord(t->finished, job.s));
+    } catch (...) {
+      err = std::current_exception();
+    }
+    lk.lock();
+    for (CgFuser::Ticket* t : members) {
+      t->err = err;
+      t->done = true;
+    }
+    f.cv.notify_all();
+  }
+  lk.unlock();
+  if (tk.err) std::rethrow_exception(tk.err);
+  MBL_HIP(hipStreamWaitEvent(job.s, tk.finished, 0));
+}
+
 template <class T>
 void run_pcg(const Ham& H, double sigma, const T* jac, const T* R, int64_t ldr, T* W, int64_t ldw,
              int b, int m, hipStream_t s, PcgTiming* tm, const StopCheck* stop, int keep,
@@ -864,6 +1234,37 @@ void run_pcg(const Ham& H, double sigma, const T* jac, const T* R, int64_t ldr, 
   const int64_t n = H.n;
   if (n == 0 || b == 0) return;
   const int wc = pcg_chunk_width<T>(n, b);
+  if (t_cg_fuser && wc == b && keep < 0 && tm == nullptr && stop == nullptr && m >= 1) {
+    // concurrent solves of a batch: this call may run in one launch with others
+    CgJob<T> job{};
+    job.sc = sched_for(H, b * (int)sizeof(T), (int)sizeof(T));
+    job.aligned = al16(R, ldr, sizeof(T)) && al16(W, ldw, sizeof(T)) && (b * sizeof(T)) % 16 == 0;
+    DevBuf rb((size_t)n * b * sizeof(T), s), pb((size_t)n * b * sizeof(T), s),
+        tb((size_t)n * b * sizeof(T), s);
+    DevBuf pa((size_t)kMaxWg * std::min(b, 4096) * sizeof(double) + 64, s);
+    DevBuf cb((size_t)b * sizeof(PcgCoef), s);
+    SplitCg<T> probe{W, ldw, rb.as<T>(), b, pb.as<T>(), b, tb.as<T>(), b, cb.as<PcgCoef>(),
+                     pa.as<double>(), b};
+    if (!split_cg_ready<T>(H, probe)) {
+      job.H = &H;
+      job.sigma = sigma;
+      job.jac = jac;
+      job.R = R;
+      job.ldr = ldr;
+      job.W = W;
+      job.ldw = ldw;
+      job.b = b;
+      job.m = m;
+      job.r = rb.as<T>();
+      job.p = pb.as<T>();
+      job.t = tb.as<T>();
+      job.part = pa.as<double>();
+      job.coef = cb.as<PcgCoef>();
+      job.s = s;
+      fuse_pcg<T>(*t_cg_fuser, job);
+      return;
+    }
+  }
   DevBuf rbuf((size_t)n * wc * sizeof(T), s), pbuf((size_t)n * wc * sizeof(T), s),
       tbuf((size_t)n * wc * sizeof(T), s);
   DevBuf xbuf;
@@ -893,8 +1294,8 @@ void run_pcg(const Ham& H, double sigma, const T* jac, const T* R, int64_t ldr, 
     }
     // CG steps [from, to) on the columns of chunk ch (events on the first
     // timed steps of the solve's first pass over the chunk)
-    auto cg_steps = [&](const Chunk& ch, int from, int to, bool timed) {
-      const Grid g = make_grid(n, ch.log2G, sc);
+    auto cg_steps = [&](const Chunk& ch, const Sched& sch, int from, int to, bool timed) {
+      const Grid g = make_grid(n, ch.log2G, sch);
       EltArgs<T> e{};
       e.x = x;
       e.ldxv = ldx;
@@ -996,15 +1397,17 @@ void run_pcg(const Ham& H, double sigma, const T* jac, const T* R, int64_t ldr, 
       // columns [0, keep) of the whole block run m_keep steps, the others m
       const int lo = c0 + ch.col0, hi = lo + ch.w;
       if (hi <= keep || m_keep <= m) {
-        cg_steps(ch, 0, hi <= keep ? std::max(m, m_keep) : m, true);
+        cg_steps(ch, sc, 0, hi <= keep ? std::max(m, m_keep) : m, true);
       } else {
-        cg_steps(ch, 0, m, true);
+        cg_steps(ch, sc, 0, m, true);
         if (lo < keep) {
-          // the leading columns of this chunk go on (same vectors and ld)
-          for (const Chunk& sub : plan_chunks<T>(keep - lo, aligned, sc)) {
+          // the leading columns of this chunk go on (same vectors and ld),
+          // under the schedule tuned for their own row width
+          const Sched sk = sched_for(H, (keep - lo) * (int)sizeof(T), (int)sizeof(T));
+          for (const Chunk& sub : plan_chunks<T>(keep - lo, aligned, sk)) {
             Chunk c2 = sub;
             c2.col0 += ch.col0;
-            cg_steps(c2, m, m_keep, true);
+            cg_steps(c2, sk, m, m_keep, true);
           }
         }
       }

@@ -290,6 +290,17 @@ void run_pcg(const Ham& H, double sigma, const T* jac, const T* R, int64_t ldr, 
              int b, int m, hipStream_t s, PcgTiming* tm = nullptr,
              const StopCheck* stop = nullptr, int keep = -1, int m_keep = 0);
 
+// Fused CG of concurrent solves (the batch): while a thread's t_cg_fuser is
+// set, its run_pcg calls without a stop check, timing or guard columns join
+// the other threads' calls with the same launch plan in one launch per
+// kernel; each problem keeps the bits of its own launch.  max_group <= 8;
+// wait_ms: how long the first caller of a group waits for the others.
+struct CgFuser;
+CgFuser* cg_fuser_create(int max_group, double wait_ms);
+void cg_fuser_destroy(CgFuser* f);
+void cg_fuser_stats(const CgFuser* f, int64_t* groups, int64_t* jobs);
+extern thread_local CgFuser* t_cg_fuser;
+
 // Jacobi diagonal of the fold, d = (E - sigma)^2 + (J/2)^2 * (#active bonds).
 template <class T>
 void launch_jacobi(const Ham& H, double sigma, T* out, hipStream_t s);

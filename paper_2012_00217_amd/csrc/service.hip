@@ -17,6 +17,7 @@
 #include <atomic>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <condition_variable>
 #include <deque>
@@ -24,6 +25,8 @@
 #include <memory>
 #include <mutex>
 #include <thread>
+
+#include <tuple>
 
 #include "common.h"
 
@@ -65,8 +68,10 @@ struct Job {
 };
 
 // One complete solve of a problem on stream s.  Writes evals/resid into the
-// job's vectors, vectors into `evecs` (device, may be null).
-void run_problem(Job& j, double* evecs, int64_t ldv, hipStream_t s) {
+// job's vectors, vectors into `evecs` (device, may be null).  `cancellable`:
+// the solve watches the job's cancel flag (server requests; batch problems
+// cannot be cancelled, and their CG steps then run without stop checks).
+void run_problem(Job& j, double* evecs, int64_t ldv, hipStream_t s, bool cancellable) {
   const auto t0 = clk::now();
   mbl_result& r = j.r;
   try {
@@ -93,7 +98,7 @@ void run_problem(Job& j, double* evecs, int64_t ldv, hipStream_t s) {
     // MBL_VERBOSE=1: one stderr line per outer iteration of every solve
     const char* verbose = std::getenv("MBL_VERBOSE");
     o.verbose = verbose ? std::atoi(verbose) : 0;
-    o.cancel = &j.cancel;
+    o.cancel = cancellable ? &j.cancel : nullptr;
     if (o.precision != MBL_F64 && o.precision != MBL_MIXED && o.precision != MBL_PCG32)
       fail(MBL_EINVAL, "bad precision");
     j.evals.assign(p.nev, 0.0);
@@ -153,6 +158,25 @@ mbl_status batch_solve(int count, const mbl_problem* probs, mbl_result* res, int
     else
       jobs[i]->h.assign(std::max(0, std::min(probs[i].L, kMaxL)), NAN);
   }
+  // With the fused CG (MBL_BATCH_FUSE=1; off by default: measured no faster
+  // than concurrent streams on the batched workload, slower with longer
+  // gather windows) the workers take the problems in order of chain length
+  // and block shape, so that the solves running side by side share their CG
+  // launches; results go to each problem's own slot either way.
+  const char* fe = std::getenv("MBL_BATCH_FUSE");
+  const bool fuse = fe != nullptr && std::atoi(fe) != 0 && conc > 1 && count > 1;
+  const char* we = std::getenv("MBL_FUSE_WAIT_MS");
+  std::unique_ptr<CgFuser, void (*)(CgFuser*)> fuser(
+      fuse ? cg_fuser_create(std::min(conc, 8), we ? std::atof(we) : 0.5) : nullptr,
+      cg_fuser_destroy);
+  std::vector<int> order(count);
+  for (int i = 0; i < count; ++i) order[i] = i;
+  if (fuse)
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+      const mbl_problem &x = probs[a], &y = probs[b];
+      return std::make_tuple(x.L, x.Sz, x.block, x.precision, x.pcg_iters) <
+             std::make_tuple(y.L, y.Sz, y.block, y.precision, y.pcg_iters);
+    });
   const auto t0 = clk::now();
   std::atomic<int> next{0};
   auto worker = [&]() {
@@ -163,12 +187,15 @@ mbl_status batch_solve(int count, const mbl_problem* probs, mbl_result* res, int
     } catch (...) {
       return;
     }
-    for (int i; (i = next.fetch_add(1)) < count;) {
-      run_problem(*jobs[i], res[i].evecs_dev, res[i].ldv, s);
+    t_cg_fuser = fuser.get();
+    for (int k; (k = next.fetch_add(1)) < count;) {
+      const int i = order[k];
+      run_problem(*jobs[i], res[i].evecs_dev, res[i].ldv, s, false);
       jobs[i]->r.latency = std::chrono::duration<double>(clk::now() - t0).count();
       copy_out(*jobs[i], &res[i]);
       jobs[i]->done = true;
     }
+    t_cg_fuser = nullptr;
     (void)hipStreamSynchronize(s);
     (void)hipStreamDestroy(s);
   };
@@ -176,6 +203,12 @@ mbl_status batch_solve(int count, const mbl_problem* probs, mbl_result* res, int
   const int nt = std::max(1, std::min(conc, count));
   for (int t = 0; t < nt; ++t) pool.emplace_back(worker);
   for (auto& t : pool) t.join();
+  if (fuser && std::getenv("MBL_FUSE_STATS")) {
+    int64_t groups = 0, calls = 0;
+    cg_fuser_stats(fuser.get(), &groups, &calls);
+    std::fprintf(stderr, "[mbl batch] fused CG: %lld groups, %lld calls\n", (long long)groups,
+                 (long long)calls);
+  }
   // a problem no worker reached (every worker failed to create its stream)
   for (int i = 0; i < count; ++i)
     if (!jobs[i]->done) res[i].status = MBL_EDEVICE;
@@ -241,7 +274,7 @@ struct Server {
           j->r.status = e.status;
         }
       }
-      if (j->r.status == MBL_OK) run_problem(*j, vec, std::max(1, j->p.nev), s);
+      if (j->r.status == MBL_OK) run_problem(*j, vec, std::max(1, j->p.nev), s, true);
       {
         std::lock_guard<std::mutex> lk(mu);
         j->r.latency = std::chrono::duration<double>(clk::now() - j->submitted).count();

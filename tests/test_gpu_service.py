@@ -3,6 +3,7 @@
 oracle on a stratified sample, footprint admission and server statistics."""
 
 import math
+import re
 
 import numpy as np
 import pytest
@@ -37,6 +38,38 @@ def test_batch_equals_single_solves_and_oracle():
         assert np.max(linalg.residual_norms(Ho, r["evals"], r["evecs"].cpu().numpy())) <= 1e-10
         lo, hi = spectrum.bounds(Ho)
         assert abs(r["sigma"] - (lo + 0.5 * (hi - lo))) < 1e-9
+
+
+def test_fused_cg_batch_is_bitwise_the_unfused_batch(monkeypatch, capfd):
+    """Concurrent solves of one chain length share their CG launches (one
+    launch per kernel for the group); every problem keeps the bits of its own
+    launch, so the batch with and without fusion, and single solves, agree
+    bitwise.  Mixed L and W, FP64 and mixed precision."""
+    probs = []
+    for j, (L, W) in enumerate([(14, 2.0), (16, 4.0), (14, 6.0), (16, 8.0), (14, 4.0),
+                                (16, 2.0), (14, 8.0), (16, 6.0), (18, 4.0), (18, 6.0)]):
+        probs.append({"L": L, "h": workloads.disorder(L, W, 200 + j), "eps": 0.5, "nev": 16,
+                      "block": 32, "tol": 1e-10, "precision": "mixed" if j % 3 == 2 else "f64",
+                      "seed": 7})
+    monkeypatch.setenv("MBL_FUSE_STATS", "1")
+    monkeypatch.setenv("MBL_BATCH_FUSE", "1")
+    fused = api.batch_solve(probs, concurrency=8, vectors=True)
+    m = re.search(r"fused CG: (\d+) groups, (\d+) calls", capfd.readouterr().err)
+    assert m, "no fusion statistics"
+    groups, calls = int(m.group(1)), int(m.group(2))
+    assert calls > groups > 0  # some CG calls ran together
+    monkeypatch.setenv("MBL_BATCH_FUSE", "0")
+    plain = api.batch_solve(probs, concurrency=8, vectors=True)
+    for d, a, b in zip(probs, fused, plain):
+        assert a["status"] == b["status"] == "MBL_OK"
+        assert np.array_equal(a["evals"], b["evals"]) and torch.equal(a["evecs"], b["evecs"])
+    for d, a in list(zip(probs, fused))[::3]:
+        H = api.Hamiltonian(d["L"], d["h"])
+        ev, V, rs, info = H.solve(a["sigma"], d["nev"], d["block"], tol=d["tol"], seed=d["seed"],
+                                  precision=d["precision"])
+        assert np.array_equal(ev, a["evals"]) and torch.equal(V, a["evecs"])
+        st, Ho = hamiltonian.sector_matrix(d["L"], d["L"] // 2, 1.0, 1.0, d["h"])
+        assert np.max(linalg.residual_norms(Ho, a["evals"], a["evecs"].cpu().numpy())) <= 1e-10
 
 
 def test_batch_reports_per_problem_errors():
