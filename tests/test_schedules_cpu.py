@@ -55,3 +55,22 @@ def test_tuner_writes_a_table_the_checks_accept(tmp_path):
     assert rows[:-1] == [(20, 184756, 512, 8, 512, 64, 0, 256),
                          (24, 2704156, 512, 4, 512, 64, 64, 64)]
     assert rows[-1][:4] == (0, 0, 0, 0)
+
+
+def test_tuner_reads_back_the_committed_table_and_merges(tmp_path):
+    """read_table parses every entry of the committed table; a merge keeps the
+    entries of shapes that were not tuned again and replaces the others."""
+    autotune = pytest.importorskip("paper_2012_00217_amd.autotune")
+    rows = autotune.read_table(TABLE)
+    assert [(r["L"], r["n"], r["row_bytes"], r["elem"]) + tuple(r["sched"]) for r in rows] == \
+        _entries()[:-1]
+    out = tmp_path / "table.inc"
+    autotune.write_table(rows, str(out))
+    assert _entries(str(out)) == _entries()
+    new = dict(rows[0], sched=(128, 16, 0, 64), ms=0.001)
+    key = lambda r: (r["L"], r["row_bytes"], r["elem"])
+    merged = [r for r in rows if key(r) != key(new)] + [new]
+    autotune.write_table(merged, str(out))
+    back = {key(r): tuple(r["sched"]) for r in autotune.read_table(str(out))}
+    assert back[key(new)] == (128, 16, 0, 64)
+    assert len(back) == len(rows)
