@@ -609,6 +609,8 @@ def main():
     ap.add_argument("--modes", default="onepass,split", help="cgstep: apply kernels to time")
     ap.add_argument("--precision-L", type=int, default=22,
                     help="precision: chain length of the mixed-against-FP64 comparison")
+    ap.add_argument("--nev", type=int, default=0, help="single solves: override the pair count")
+    ap.add_argument("--block", type=int, default=0, help="single solves: override the block width")
     ap.add_argument("--guard-cg", type=float, default=0.0,
                     help="CG steps of the guard columns as a fraction (0: library default)")
     args = ap.parse_args()
@@ -641,6 +643,10 @@ def main():
     if args.precision and args.precision != wl["precision"]:
         wl["desc"] = wl["desc"].rsplit(", ", 1)[0] + f", precision {args.precision}"
         wl["precision"] = args.precision
+    if args.nev or args.block:
+        wl["nev"] = args.nev or wl["nev"]
+        wl["block"] = args.block or wl["block"]
+        wl["desc"] += f" (overridden: {wl['nev']} pairs, block {wl['block']})"
     L = wl["L"]
 
     def note(msg):

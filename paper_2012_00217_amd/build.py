@@ -2,9 +2,17 @@
 
 Run as ``python -m paper_2012_00217_amd.build``.  Objects go to ``_build/``
 at the repository root; the shared library is written next to this file.
+A measurement variant of the kernels (a compile-time switch of the sources) is
+built with extra flags into another file, e.g.
+
+    MBL_HIPCC_FLAGS=-DMBL_CG_NT_LOAD=1 MBL_BUILD_OUT=/tmp/nt/libmbl.so \
+        python -m paper_2012_00217_amd.build
+
+and loaded instead of the default library with MBL_LIBRARY=/tmp/nt/libmbl.so.
 """
 
 import concurrent.futures as cf
+import hashlib
 import os
 import subprocess
 import sys
@@ -17,13 +25,17 @@ BUILD = os.path.join(ROOT, "_build")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("MBL_OFFLOAD_ARCH", "gfx950")
+# MBL_HIPCC_FLAGS: extra compiler flags, e.g. "-DMBL_CG_NT_LOAD=1" to build a
+# variant of the kernels for a measurement (MBL_LIBRARY then selects it).
+EXTRA = os.environ.get("MBL_HIPCC_FLAGS", "").split()
+OUT = os.environ.get("MBL_BUILD_OUT", OUT)
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     # packed FP32 instructions are disabled for every device function
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
     "-I", os.path.join(ROOT, "include"),
-]
+] + EXTRA
 
 
 def sources():
@@ -31,7 +43,8 @@ def sources():
 
 
 def _compile(src):
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+    tag = "" if not EXTRA else "." + hashlib.sha1(" ".join(EXTRA).encode()).hexdigest()[:8]
+    obj = os.path.join(BUILD, os.path.basename(src) + tag + ".o")
     cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -45,6 +58,7 @@ def build(verbose=True):
     jobs = min(len(srcs), int(os.environ.get("MAX_JOBS", "8")), 16)
     with cf.ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
         objs = list(ex.map(_compile, srcs))
+    os.makedirs(os.path.dirname(os.path.abspath(OUT)), exist_ok=True)
     tmp = OUT + ".tmp"
     cmd = [HIPCC, "-shared", f"--offload-arch={ARCH}", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
