@@ -675,10 +675,11 @@ def main():
         torch.cuda.synchronize()
         del src, dst
         # the CG widths of the solve: every column, then the wanted ones alone
-        # when the guard columns stop early (n >= 500000, see the library)
+        # when the guard columns stop early (n >= 500000 and nev >= 64, see the
+        # library)
         widths = ([int(x) for x in args.cg_widths.split(",")] if args.cg_widths else
-                  [wl["block"]] + ([wl["nev"]] if n >= 500000 and wl["nev"] < wl["block"]
-                                   else []))
+                  [wl["block"]] + ([wl["nev"]] if n >= 500000 and 64 <= wl["nev"] < wl["block"]
+                                   and args.guard_cg != 1.0 else []))
         for W, H in hams.items():
             for w in widths:
                 R = torch.randn(n, w, dtype=torch.float64 if s == 8 else torch.float32,
