@@ -32,6 +32,7 @@
 #include <cstdlib>
 #include <exception>
 #include <map>
+#include <memory>
 #include <mutex>
 
 #include "common.h"
@@ -998,15 +999,21 @@ struct CgJob {
 
 struct CgFuser {
   struct Ticket {
-    std::vector<int64_t> key;
     void* job;
     hipEvent_t ready = nullptr, finished = nullptr;
     bool done = false;
     std::exception_ptr err;
   };
+  // A group is open to new calls until it holds max_group of them or its
+  // leader stops waiting; then it leaves `open`, and the next call with the
+  // same key starts a new group.
+  struct Group {
+    std::vector<Ticket*> members;
+    bool closed = false;
+  };
   std::mutex mu;
   std::condition_variable cv;
-  std::map<std::vector<int64_t>, std::vector<Ticket*>> open;
+  std::map<std::vector<int64_t>, std::shared_ptr<Group>> open;
   int max_group;
   std::chrono::microseconds wait;
   int64_t groups = 0, jobs = 0;
@@ -1021,6 +1028,7 @@ static_assert(sizeof(MultiApply<double>) <= 4096 && sizeof(MultiElt<double>) <= 
 template <class T>
 void run_pcg_fused(const std::vector<CgJob<T>*>& g, hipStream_t s) {
   const int np = (int)g.size();
+  if (np < 1 || np > kMaxFuse) fail(MBL_EINTERNAL, "fused pcg: group size out of range");
   const CgJob<T>& j0 = *g[0];
   const int b = j0.b, m = j0.m;
   for (const Chunk& ch : plan_chunks<T>(b, j0.aligned, j0.sc)) {
@@ -1177,7 +1185,6 @@ void fuse_pcg(CgFuser& f, CgJob<T>& job) {
   std::vector<int64_t> key = {(int64_t)sizeof(T), job.b, job.m, job.aligned ? 1 : 0,
                               job.sc.chunk_bytes, job.sc.lane_bytes, job.sc.grp, job.sc.slots};
   CgFuser::Ticket tk;
-  tk.key = key;
   tk.job = &job;
   MBL_HIP(hipEventCreateWithFlags(&tk.ready, hipEventDisableTiming));
   MBL_HIP(hipEventCreateWithFlags(&tk.finished, hipEventDisableTiming));
@@ -1190,16 +1197,33 @@ void fuse_pcg(CgFuser& f, CgJob<T>& job) {
   } ev{tk};
   MBL_HIP(hipEventRecord(tk.ready, job.s));  // R and the caller's buffers are ready
   std::unique_lock<std::mutex> lk(f.mu);
-  auto& grp = f.open[key];
-  grp.push_back(&tk);
-  if (grp.size() > 1) {
-    if ((int)grp.size() >= f.max_group) f.cv.notify_all();
+  std::shared_ptr<CgFuser::Group> grp;
+  bool leader = false;
+  auto it = f.open.find(key);
+  if (it == f.open.end()) {
+    grp = std::make_shared<CgFuser::Group>();
+    f.open[key] = grp;
+    leader = true;
+  } else {
+    grp = it->second;
+  }
+  grp->members.push_back(&tk);
+  if ((int)grp->members.size() >= f.max_group) {  // full: no further call joins it
+    grp->closed = true;
+    f.open.erase(key);
+    f.cv.notify_all();
+  }
+  if (!leader) {
     f.cv.wait(lk, [&] { return tk.done; });
   } else {
-    // leader: gather peers, then run the group on this caller's stream
-    f.cv.wait_for(lk, f.wait, [&] { return (int)f.open[key].size() >= f.max_group; });
-    std::vector<CgFuser::Ticket*> members = std::move(f.open[key]);
-    f.open.erase(key);
+    // leader: gather peers for a short time, then run the group on this
+    // caller's stream
+    f.cv.wait_for(lk, f.wait, [&] { return grp->closed; });
+    if (!grp->closed) {  // still the open group of this key
+      grp->closed = true;
+      f.open.erase(key);
+    }
+    const std::vector<CgFuser::Ticket*> members = grp->members;
     ++f.groups;
     f.jobs += (int64_t)members.size();
     lk.unlock();

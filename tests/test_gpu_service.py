@@ -40,7 +40,8 @@ def test_batch_equals_single_solves_and_oracle():
         assert abs(r["sigma"] - (lo + 0.5 * (hi - lo))) < 1e-9
 
 
-def test_fused_cg_batch_is_bitwise_the_unfused_batch(monkeypatch, capfd):
+@pytest.mark.parametrize("conc", [8, 12])
+def test_fused_cg_batch_is_bitwise_the_unfused_batch(conc, monkeypatch, capfd):
     """Concurrent solves of one chain length share their CG launches (one
     launch per kernel for the group); every problem keeps the bits of its own
     launch, so the batch with and without fusion, and single solves, agree
@@ -53,13 +54,15 @@ def test_fused_cg_batch_is_bitwise_the_unfused_batch(monkeypatch, capfd):
                       "seed": 7})
     monkeypatch.setenv("MBL_FUSE_STATS", "1")
     monkeypatch.setenv("MBL_BATCH_FUSE", "1")
-    fused = api.batch_solve(probs, concurrency=8, vectors=True)
+    # with 10 workers and groups of at most 8 calls, full groups close and the
+    # next calls start new ones
+    fused = api.batch_solve(probs, concurrency=conc, vectors=True)
     m = re.search(r"fused CG: (\d+) groups, (\d+) calls", capfd.readouterr().err)
     assert m, "no fusion statistics"
     groups, calls = int(m.group(1)), int(m.group(2))
     assert calls > groups > 0  # some CG calls ran together
     monkeypatch.setenv("MBL_BATCH_FUSE", "0")
-    plain = api.batch_solve(probs, concurrency=8, vectors=True)
+    plain = api.batch_solve(probs, concurrency=conc, vectors=True)
     for d, a, b in zip(probs, fused, plain):
         assert a["status"] == b["status"] == "MBL_OK"
         assert np.array_equal(a["evals"], b["evals"]) and torch.equal(a["evecs"], b["evecs"])
