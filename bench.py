@@ -69,6 +69,18 @@ def apply_src_hash():
     return h.hexdigest()[:16]
 
 
+def cg_launch_widths(steps, column_steps, block, nev):
+    """CG launches per column width of a solve whose CG runs on all `block`
+    columns until the guard columns stop, then on the `nev` wanted ones:
+    x + y = steps, block x + nev y = column_steps.  {} if the counts do not
+    fit that pattern."""
+    y = (block * steps - column_steps) / float(block - nev) if block > nev else 0.0
+    if abs(y - round(y)) > 1e-6 or not 0 <= y <= steps:
+        return {}
+    y = int(round(y))
+    return {block: steps - y, **({nev: y} if y > 0 else {})}
+
+
 def read_traffic(kernel, workload, precision, width=None):
     """HBM bytes per launch from the committed counter summary, or None if the
     summary is missing, covers another workload or precision, or was taken
@@ -777,18 +789,9 @@ def main():
     kb = bytes_all / max(1, nl)
     avg_ms = ms_all / max(1, nl)
     achieved = kb / (avg_ms * 1e-3) / 1e9
-    # CG launches per width: every column (b) until the guard columns stop,
-    # then the nev wanted ones: x + y = launches, b x + nev y = column-steps
-    b_, v_ = wl["block"], wl["nev"]
-    widths = {}
-    if args.lock:
-        widths = None
-    elif nl == steps_cg:
-        y = (b_ * steps_cg - cols_cg) / float(b_ - v_) if b_ > v_ else 0.0
-        if abs(y - round(y)) < 1e-6 and 0 <= y <= steps_cg:
-            widths = {b_: steps_cg - int(round(y))}
-            if y > 0:
-                widths[v_] = int(round(y))
+    b_ = wl["block"]
+    widths = None if args.lock else (
+        cg_launch_widths(steps_cg, cols_cg, b_, wl["nev"]) if nl == steps_cg else {})
     traffic = None
     if widths:
         per_w = {w: read_traffic(dom, args.workload, wl["precision"], w) for w in widths}

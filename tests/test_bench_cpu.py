@@ -45,3 +45,17 @@ def test_traffic_is_taken_only_from_matching_counter_files():
             assert t is not None and t > 0
         else:
             assert t is None
+
+
+def test_cg_launch_widths_from_the_solve_counts():
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
+    b = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(b)
+    # the L=24 solve: 17,193 steps on 128 columns, 154,605 on the 64 wanted ones
+    assert b.cg_launch_widths(171798, 12095424, 128, 64) == {128: 17193, 64: 154605}
+    # no guard columns: every step on the whole block
+    assert b.cg_launch_widths(1000, 64000, 64, 32) == {64: 1000}
+    # counts that no mix of the two widths gives
+    assert b.cg_launch_widths(1000, 64001, 64, 32) == {}
+    assert b.cg_launch_widths(1000, 10, 64, 32) == {}
