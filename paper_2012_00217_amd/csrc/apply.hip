@@ -192,13 +192,6 @@ __device__ inline void block_reduce_store(double (&red)[NV * VE], int log2G, int
 #define MBL_APPLY_ALPHA_LDS 1
 #endif
 
-// MBL_APPLY_COMPACT=1: each row's offset table lists its active bonds first
-// (ascending), so the gather loop stops after them instead of stepping over
-// every bond slot.
-#ifndef MBL_APPLY_COMPACT
-#define MBL_APPLY_COMPACT 0
-#endif
-
 #ifndef MBL_APPLY_BB_BYTES
 #define MBL_APPLY_BB_BYTES 256
 #endif
@@ -278,17 +271,7 @@ __device__ __forceinline__ void apply_body(const ApplyArgs<T>& a, const int bid,
           if (rr + d >= 0 && rr + d < a.n) o = d;
         }
       }
-#if MBL_APPLY_COMPACT
-      // the row's active bonds first, in ascending bond order (the 32 lanes
-      // of one row are one half of the wave), then kNoFlip to the end
-      const unsigned long long act = __ballot(o != kNoFlip);
-      const uint32_t rowmask = (uint32_t)(act >> (lane & 32));
-      const int cnt = __popc(rowmask);
-      if (o != kNoFlip) offtab[r * 32 + __popc(rowmask & ((1u << i) - 1u))] = o;
-      if (i >= cnt) offtab[r * 32 + i] = kNoFlip;
-#else
       offtab[it] = o;
-#endif
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -309,9 +292,6 @@ __device__ __forceinline__ void apply_body(const ApplyArgs<T>& a, const int bid,
         int o[BB];
 #pragma unroll
         for (int v = 0; v < BB; ++v) o[v] = myoff[i0 + v];
-#if MBL_APPLY_COMPACT
-        if (o[0] == kNoFlip) break;  // the row's active bonds are all done
-#endif
         P v[BB][NV];
 #pragma unroll
         for (int b2 = 0; b2 < BB; ++b2) {
