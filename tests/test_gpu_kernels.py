@@ -6,6 +6,8 @@ PCG, Gram, combine and the small eigensolver against the oracle's step-by-step
 or numpy definitions.
 """
 
+import math
+
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -402,3 +404,33 @@ def test_invalid_arguments_raise():
         H.solve(0.0, nev=9, block=8)
     with pytest.raises(api.MblError):
         H.solve(0.0, nev=2, block=40)  # 2 * block > n = 70
+
+
+@pytest.mark.parametrize("L", [30, 32])
+def test_largest_chains(L):
+    """The largest sectors the library takes: L = 30 (n = 155,117,520) and the
+    maximum L = 32 (n = 601,080,390; state words use bit 31).  The sector list
+    bit-exact against the oracle's enumeration, ranks of sampled states
+    (and -1 off the sector), and 400 sampled rows of the FP64 apply (two
+    columns) against the oracle's row-wise apply."""
+    h = workloads.disorder(L, 4.0, 0)
+    H = api.Hamiltonian(L, h)
+    st = basis.enumerate_sector(L, L // 2)
+    assert H.n == len(st) == math.comb(L, L // 2)
+    assert np.array_equal(H.states(), st)
+    rng = np.random.default_rng(L)
+    edges = np.array([0, 1, 31, 32, 63, 64, H.n // 2, H.n - 2, H.n - 1])
+    rows = np.unique(np.concatenate([edges, rng.integers(0, H.n, 391)]))
+    q = np.concatenate([st[rows], np.array([st[-1] | np.uint64(1), (1 << L) - 1], np.uint64)])
+    assert np.array_equal(H.rank(q), np.concatenate([rows, [-1, -1]]))
+    g = torch.Generator(device=DEV)
+    g.manual_seed(L)
+    X = torch.randn(H.n, 2, dtype=torch.float64, device=DEV, generator=g)
+    Y = H.apply(X, -0.29)
+    fetch = lambda idx: X[torch.from_numpy(np.asarray(idx)).to(DEV)].cpu().numpy()
+    Yr, B = hamiltonian.apply_rows(L, st, 1.0, 1.0, h, rows, -0.29, fetch)
+    got = Y[torch.from_numpy(rows).to(DEV)].cpu().numpy()
+    assert np.all(np.abs(got - Yr) <= 1e-13 * B + 1e-300)
+    del X, Y, st
+    H.close()
+    torch.cuda.empty_cache()
