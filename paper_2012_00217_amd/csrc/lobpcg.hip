@@ -416,16 +416,32 @@ class Phase {
     // CG keeps its tuned shapes.
     std::vector<int>& act = h_act_;
     act.clear();
+    const int grain = 128 / (int)sizeof(TP);
+    int act_wanted = 0;  // unlocked wanted pairs, leading act when guard columns apply
     {
       std::vector<char> drop(b, 0);
       if (p_.fold && m > 0 && !locked_.empty()) {
-        const int grain = 128 / (int)sizeof(TP);
         int keep = b - (int)locked_.size();
         keep = std::min(b, std::max(grain, (keep + grain - 1) / grain * grain));
         for (int k = 0; k < b - keep; ++k) drop[locked_[k]] = 1;
       }
-      for (int j = 0; j < b; ++j)
-        if (!drop[j]) act.push_back(j);
+      if (p_.fold && m > 0 && !locked_.empty() && p_.guard_frac < 1.0) {
+        // guard columns with soft locking: the unlocked wanted pairs first (they
+        // run every CG step), then the locked ones still active, then the rest
+        std::vector<char> wanted(b, 0), locked(b, 0);
+        for (int j : h_sel_) wanted[j] = 1;
+        for (int j : locked_) locked[j] = 1;
+        for (int j = 0; j < b; ++j)
+          if (!drop[j] && wanted[j] && !locked[j]) act.push_back(j);
+        act_wanted = (int)act.size();
+        for (int j = 0; j < b; ++j)
+          if (!drop[j] && wanted[j] && locked[j]) act.push_back(j);
+        for (int j = 0; j < b; ++j)
+          if (!drop[j] && !wanted[j]) act.push_back(j);
+      } else {
+        for (int j = 0; j < b; ++j)
+          if (!drop[j]) act.push_back(j);
+      }
     }
     const int keep = (int)act.size();
     const auto t_res = clk::now();
@@ -463,11 +479,17 @@ class Phase {
       PcgTiming* tm = st_.timing ? &st_.tm[sizeof(TP) == 4 ? 1 : 0] : nullptr;
       const StopCheck* stop = (p_.stop.has_deadline || p_.stop.flag) ? &p_.stop : nullptr;
       // guard columns (beyond the nev smallest fold Ritz values, which lead R
-      // in its A-Ritz order) may stop after a fraction of the CG steps
+      // in its A-Ritz order; with soft locking, beyond the unlocked wanted
+      // pairs, which lead the rotated block, in whole 128-byte rows) may stop
+      // after a fraction of the CG steps
       int m_all = m, keep = -1;
-      if (p_.guard_frac < 1.0 && Rin == R && p_.nev < wq) {
-        m_all = std::max(1, (int)std::lround(p_.guard_frac * m));
-        keep = p_.nev;
+      if (p_.guard_frac < 1.0) {
+        const int lead = (Rin == R) ? p_.nev
+                                    : std::max(grain, (act_wanted + grain - 1) / grain * grain);
+        if (lead < wq && (Rin == R || act_wanted > 0)) {
+          m_all = std::max(1, (int)std::lround(p_.guard_frac * m));
+          keep = lead;
+        }
       }
       if constexpr (std::is_same<TB, TP>::value) {
         run_pcg<TP>(H_, p_.sigma, jac, Rin, ldRin, W, ld, wq, m_all, s_, tm, stop, keep, m);

@@ -147,6 +147,30 @@ def test_soft_locking_dense_parity(precision):
     _check(Ho, sigma, nev, ev0, V0, rs0, w_ref, V_ref)
 
 
+@pytest.mark.parametrize("precision", ["f64", "mixed"])
+def test_soft_locking_with_guard_columns(precision):
+    """Soft locking together with guard columns that run a quarter of the CG
+    steps: the locked path puts the unlocked wanted pairs first so that only
+    the rest stop early.  The same pairs as dense diagonalisation, and fewer
+    CG column-steps than with locking alone."""
+    L, nev, b = 14, 32, 96
+    h = workloads.disorder(L, 4.0, 0)
+    st, Ho = hamiltonian.sector_matrix(L, L // 2, 1.0, 1.0, h)
+    emin, emax = spectrum.bounds(Ho)
+    sigma = spectrum.shift_from_density(emin, emax, 0.5)
+    w_ref, V_ref = spectrum.nearest(Ho, sigma, nev)
+    H = api.Hamiltonian(L, h)
+    ev, V, rs, info = H.solve(sigma, nev, b, tol=1e-10, precision=precision, lock=True,
+                              guard_cg=0.25)
+    assert info["status"] == "MBL_OK"
+    _check(Ho, sigma, nev, ev, V, rs, w_ref, V_ref)
+    ev1, V1, rs1, info1 = H.solve(sigma, nev, b, tol=1e-10, precision=precision, lock=True,
+                                  guard_cg=1.0)
+    _check(Ho, sigma, nev, ev1, V1, rs1, w_ref, V_ref)
+    per_step = info["pcg_columns"] / info["pcg_steps"]
+    assert per_step < info1["pcg_columns"] / info1["pcg_steps"], (info, info1)
+
+
 def test_soft_locking_delta_zero_l18():
     """Soft locking on a larger sector (L = 18, n = 48620, 32 pairs, block 48) at
     Delta = 0, against the exact single-particle subset sums.  Short inner
