@@ -203,8 +203,11 @@ typedef struct {
                             rounded up to whole 128-byte rows of the CG's
                             scalars (least converged locked pairs stay
                             active), so the inner CG runs on fewer columns.
-                            Results satisfy the same tolerance; iterates
-                            differ from lock = 0.  Default 0.               */
+                            With guard columns (guard_cg) the unlocked
+                            wanted pairs lead the rotated block and run all
+                            the CG steps.  Results satisfy the same
+                            tolerance; iterates differ from lock = 0.
+                            Default 0.                                       */
   double max_seconds;    /* > 0: wall-clock limit of the call.  Checked
                             between outer iterations and every 32 CG steps;
                             when it passes, the solve finishes the CG chunk
@@ -222,8 +225,9 @@ typedef struct {
                             nev >= 64 (measured 1.32x faster at L = 22, nev
                             64, block 128), else 1 (with nev 16, block 32 the
                             narrowed CG saves too little per step: 1.68x
-                            slower at L = 22).  Applies without soft
-                            locking.                                         */
+                            slower at L = 22).  With soft locking the guard
+                            columns are those beyond the unlocked wanted
+                            pairs.                                           */
 } mbl_solve_opts;
 
 typedef struct {
