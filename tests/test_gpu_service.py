@@ -54,6 +54,9 @@ def test_fused_cg_batch_is_bitwise_the_unfused_batch(conc, monkeypatch, capfd):
                       "seed": 7})
     monkeypatch.setenv("MBL_FUSE_STATS", "1")
     monkeypatch.setenv("MBL_BATCH_FUSE", "1")
+    # a long gather window: the solves of one L start together, so their CG
+    # calls arrive within it and share launches whatever the thread timing
+    monkeypatch.setenv("MBL_FUSE_WAIT_MS", "200")
     # with 10 workers and groups of at most 8 calls, full groups close and the
     # next calls start new ones
     fused = api.batch_solve(probs, concurrency=conc, vectors=True)
