@@ -247,6 +247,10 @@ class Hamiltonian:
         > 0 limits the wall time and `cancel` (a ctypes.c_int another thread
         may set nonzero) stops the solve; both return the best pairs so far
         with status MBL_ECANCELLED (raised unless raise_on_noconv is False).
+        guard_cg in (0, 1] gives the block columns beyond nev that share of the
+        CG steps (0: the library's default by sector size and nev; see
+        mbl_solve_opts.guard_cg).  timing=True fills the info dict with event
+        times of the CG kernels and of the apply, Gram and small dense phases.
 
         Returns (evals [nev] numpy, evecs (n, nev) float64 tensor or None,
         resid [nev] numpy, info dict).
