@@ -614,7 +614,7 @@ def main():
     ap.add_argument("--cg-widths", default="",
                     help="counter runs: block widths of the CG calls (default: the block, "
                          "then nev when the solve narrows the CG to the wanted columns)")
-    ap.add_argument("--budget-s", type=float, default=540.0,
+    ap.add_argument("--budget-s", type=float, default=560.0,
                     help="wall seconds of the whole command (the timed steps stop in time)")
     ap.add_argument("--cases", default="24:128:f32,22:128:f32,20:64:f64",
                     help="cgstep: L:block:dtype list")
@@ -731,7 +731,7 @@ def main():
     # timed steps stop early enough to leave time for the checks below; a
     # solve that would run past the budget stops at its own time limit and
     # returns its best pairs (only those the oracle confirms are counted).
-    reserve = 45.0
+    reserve = 20.0
     t0 = time.perf_counter()
     runs, elapsed = [], 0.0
     while len(runs) < args.steps:
