@@ -84,3 +84,25 @@ def test_noalloc_gram_rejects_shapes_beyond_the_scratch():
     with pytest.raises(api.MblError, match="bytes of partial sums"):
         api.gram_noalloc(A, A, out)
     assert torch.count_nonzero(out) == 0
+
+
+def test_noalloc_gram_under_graph_capture():
+    """The use the entry point is for: captured into a graph (torch.cuda.graph)
+    and replayed, with eager work and synchronisations between the replays;
+    every replay equals mbl_gram on the inputs of that moment."""
+    A = _block(50000, 64, 7, torch.float32)
+    B = _block(50000, 96, 8, torch.float32)
+    out = torch.zeros((64, 96), dtype=torch.float64, device="cuda")
+    api.gram_noalloc(A, B, out)  # first use on this GPU outside the capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        api.gram_noalloc(A, B, out)
+    for k in range(3):
+        A.mul_(1.5)
+        B.add_(0.25)
+        _ = (A * 2).sum().item()  # eager work and a synchronisation between replays
+        out.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, api.gram(A, B)), k
