@@ -191,8 +191,10 @@ typedef struct {
   int precision;         /* mbl_precision: MBL_F64, MBL_MIXED or MBL_PCG32   */
   int verbose;           /* 1: one line per outer iteration on stderr        */
   int timing;            /* 1: time the two fused CG apply kernels with HIP
-                            events on the solve's stream (first 64 CG steps
-                            of every inner solve)                            */
+                            events on the solve's stream (the first 64 CG
+                            steps of every inner CG call and column chunk,
+                            extrapolated to all its steps), and the apply,
+                            Gram and small dense phases                      */
   uint64_t seed;         /* starting block (device counter-based generator)  */
   int lock;              /* 1: soft locking.  Wanted pairs whose tracked
                             residual is <= tol/10 keep their place in X and
@@ -249,7 +251,8 @@ typedef struct {
      6nws + (12 + s)n for a launch over w columns of s-byte scalars          */
   double cg_apply1_bytes[2], cg_apply2_bytes[2];
   int64_t pcg_columns;   /* CG steps times block columns, summed over inner
-                            solves (fewer than pcg_steps * block with lock) */
+                            solves (fewer than pcg_steps * block with lock or
+                            guard columns)                                   */
   /* opts.timing: device seconds (HIP events) of the applies outside the CG
      (residual blocks, new directions, fresh residuals), the Gram products and
      the small dense kernels (eigensolver, Cholesky, small products)        */
