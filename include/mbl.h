@@ -223,9 +223,10 @@ typedef struct {
                             the guard columns of the block (those beyond the
                             nev smallest fold Ritz values); the nev leading
                             columns always run all pcg_iters steps.  0 = by
-                            shape: 0.1 for sectors of n >= 500000 with
-                            nev >= 64 (measured 1.32x faster at L = 22, nev
-                            64, block 128), else 1 (with nev 16, block 32 the
+                            shape: 0.05 for sectors of n >= 500000 with
+                            nev >= 64 (measured 1.47x faster at L = 22 and
+                            L = 24, nev 64, block 128), else 1 (with nev 16,
+                            block 32 the
                             narrowed CG saves too little per step: 1.68x
                             slower at L = 22).  With soft locking the guard
                             columns are those beyond the unlocked wanted

@@ -711,7 +711,7 @@ mbl_status solve_interior(const Ham& H, double sigma, int nev, int b, double tol
   // sectors, and at least 64 wanted columns, so that the CG on them alone
   // still runs on wide rows)
   p.guard_frac = o.guard_cg > 0 ? std::min(1.0, o.guard_cg)
-                                : (H.n >= 500000 && nev >= 64 ? 0.1 : 1.0);
+                                : (H.n >= 500000 && nev >= 64 ? 0.05 : 1.0);
   p.stop.flag = o.cancel;
   if (o.max_seconds > 0) {
     p.stop.has_deadline = true;
